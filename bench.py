@@ -1,0 +1,142 @@
+"""Throughput benchmark of the bulk-microphysics column step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c1] [--mode fp64]
+
+One step = one casim_step over the whole synthetic domain (saturation
+adjustment, the 12 process rates with limiter, sedimentation, tendency and
+surface writes) with the state already resident in HBM.  The default workload
+is the LES-like domain: 256 x 256 columns x 100 levels, 50 % clustered cloud,
+dt = 2 s, seed 1, all arithmetic in binary64.
+
+Prints one JSON line: grid-point updates/s, the roofline position of the
+sweep kernel (algorithmic HBM bytes per launch / mean kernel time from HIP
+events on the launch stream) and the CPU oracle's throughput on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+B_CLOUDY, B_CLEAR, B_COLUMN = 208, 160, 64   # algorithmic bytes per point / column
+
+
+def algorithmic_bytes(cfg, mask) -> int:
+    """Bytes a step must move: 14 reads + 12 writes (FP64) per point of a
+    cloudy column, 8 reads + 12 writes per point of a clear column, 8 surface
+    writes per column."""
+    ncloudy = int(mask.sum())
+    nclear = cfg.ncol - ncloudy
+    return cfg.nlev * (ncloudy * B_CLOUDY + nclear * B_CLEAR) + cfg.ncol * B_COLUMN
+
+
+def cpu_baseline(st, dz, dt, budget_s=12.0):
+    import oracle
+    nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    nthreads = min(nthreads, 16)
+    oracle.build(force=False)
+    oracle.step(st[:, :, :64], dz, dt, nthreads=nthreads)      # warm the library
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        oracle.step(st, dz, dt, nthreads=nthreads)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > budget_s or len(times) >= 3:
+            break
+    t = float(np.median(times))
+    pts = st.shape[1] * st.shape[2]
+    return {"value": pts / t, "unit": "grid-point updates/s", "cores": nthreads, "kind": "oracle",
+            "sample": "%d columns x %d levels of the same workload, median of %d full steps (%.2f s each)"
+                      % (st.shape[2], st.shape[1], len(times), t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c1")
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32mix"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the column step needs no exchange between GPUs "
+              "and this build runs on a single MI355X; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2010_14823_amd import casim, synth
+
+    cfg = synth.CONFIGS[args.config]
+    fields, dz, cols = synth.generate(cfg)
+    st = synth.stack(fields)
+    mask = synth.cloud_mask(cfg)
+    del fields
+    dev = torch.from_numpy(st).cuda()
+    tend = torch.empty((12, cfg.nlev, cfg.ncol), dtype=torch.float64, device="cuda")
+    sfc = torch.empty((8, cfg.ncol), dtype=torch.float64, device="cuda")
+    mode = casim.MODE_FP64 if args.mode == "fp64" else casim.MODE_FP32MIX
+    casim.init(casim.default_constants(mode=mode))
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        casim.step(dev, dz, cfg.dt, tend, sfc)
+    torch.cuda.synchronize()
+    status = casim.status()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        casim.step(dev, dz, cfg.dt, tend, sfc)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    status = casim.status()
+
+    points = cfg.ncol * cfg.nlev
+    ms_per_step = wall * 1e3 / args.steps
+    alg = algorithmic_bytes(cfg, mask)
+    achieved = alg / (kern_ms * 1e-3) / 1e9
+    line = {
+        "metric": "grid-point updates/s: FP64 plain vs FP32-mixed vs MLP surrogate @ stated error",
+        "value": points / (wall / args.steps),
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.mode == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "%s %s step: %d columns x %d levels, %s cloudy columns, dt=%g s, seed %d"
+                               % (cfg.name, args.mode, cfg.ncol, cfg.nlev,
+                                  "all" if cfg.cloud_frac is None else "%d%%" % round(100 * cfg.cloud_frac),
+                                  cfg.dt, cfg.seed),
+                   "columns": cfg.ncol, "levels": cfg.nlev, "points": points, "mode": args.mode},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sweep_kernel", "kernel_ms": kern_ms, "algorithmic_bytes": alg},
+        "status": status,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(st, dz, cfg.dt)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * casim.h -- C ABI of the MI355X (gfx950) bulk-microphysics column step.
+ *
+ * The library plays the role the CASIM port study (arXiv 2010.14823) gives the
+ * microphysics: a sub-model that a parent atmospheric model calls once per
+ * timestep for every grid column (Sec. I, Sec. II-A), which works on each
+ * column independently (Sec. II) and returns a source term (tendency) for
+ * each prognostic moisture field (Sec. III-B).  As in the paper's offload
+ * (Sec. III-A, Sec. III-B), the whole scheme -- saturation adjustment, the
+ * warm-rain and ice process rates with their conditionals, and sedimentation
+ * in sub-timesteps -- runs on the device in one pass per step, constants are
+ * copied to the device once at initialisation, and each step is ordered on a
+ * caller-supplied queue (here a HIP stream).
+ *
+ * Conventions for every entry point:
+ *  - Return value: CASIM_OK (0) or a negative CASIM_E* code; nothing throws.
+ *    Arguments are validated on the host before anything is enqueued; a
+ *    rejected call enqueues nothing.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls that take a stream return after enqueueing; their outputs are valid
+ *    once the stream reaches that point.
+ *  - One process-wide context (like the scheme's module globals, Sec. III-B).
+ *    It is not thread-safe; at most one call may be in flight at a time.
+ *  - Field layout: every 3-D field is float64 on the device, laid out
+ *    [k][ld] with the column index fastest (element (k, c) at k*ld + c),
+ *    k = 0 the lowest level.  The caller owns all field memory; the library
+ *    never frees it and reads/writes it only inside enqueued work.
+ */
+#ifndef CASIM_H
+#define CASIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CASIM_ABI_VERSION 1
+
+/* ---- error codes ------------------------------------------------------- */
+#define CASIM_OK            0
+#define CASIM_EINVAL       -1   /* bad argument (NULL, size, dt, ld, mode) */
+#define CASIM_ENOINIT      -2   /* casim_init has not succeeded            */
+#define CASIM_ECAPACITY    -3   /* request exceeds a configured capacity   */
+#define CASIM_EHIP         -4   /* HIP runtime error (text: casim_strerror)*/
+#define CASIM_ENOSURROGATE -5   /* surrogate mode without loaded weights   */
+
+/* ---- modes and stage switches (casim_constants.mode / .stages) ---------- */
+#define CASIM_MODE_FP64      0  /* plain path, all arithmetic in binary64  */
+#define CASIM_MODE_FP32MIX   1  /* process rates and fall speeds in
+                                   binary32; saturation adjustment, fluxes,
+                                   level updates and surface sums binary64 */
+#define CASIM_MODE_SURROGATE 2  /* process rates from the learned MLP      */
+
+#define CASIM_STAGE_ADJUST 1    /* clean-up + instant phase changes        */
+#define CASIM_STAGE_SATADJ 2    /* liquid saturation adjustment            */
+#define CASIM_STAGE_RATES  4    /* 12 process rates, limiter, apply        */
+#define CASIM_STAGE_SED    8    /* sedimentation of rain, ice, snow, graupel */
+#define CASIM_STAGE_ALL    15
+
+#define CASIM_MAX_NLEV     512  /* largest number of levels per column     */
+#define CASIM_NIN          14
+#define CASIM_NTEND        12
+#define CASIM_NSFC         8
+#define CASIM_NRATE        12
+
+/* Physical constants and parameters of the scheme.  casim_default_constants
+ * fills the published values named beside each group; callers may change
+ * them before casim_init. */
+typedef struct casim_constants {
+    int32_t mode;                  /* CASIM_MODE_*                          */
+    int32_t stages;                /* CASIM_STAGE_* bits                    */
+    int32_t warm;                  /* 1: warm configuration (no ice), Sec. II */
+    int32_t reserved0;
+    /* gas and phase change */
+    double R_d, R_v, cp, L_v, L_s;               /* J kg-1 K-1, J kg-1      */
+    double T_0, g;                                /* K, m s-2                */
+    /* densities, kg m-3 */
+    double rho_w, rho_i, rho_s, rho_g, rho_0;
+    /* transport: K_a (W m-1 K-1), D_v = Dv0 (T/T_0)^Dv_exp (1e5/p)        */
+    double K_a, Dv0, Dv_exp;
+    /* saturation pressure a exp(b Tc/(Tc+c)): Bolton 1980 liquid, Buck 1981 ice */
+    double esl_a, esl_b, esl_c, esi_a, esi_b, esi_c;
+    /* Khairoutdinov & Kogan 2000: AUTO = a qc^e1 Nc^e2 (Nc cm-3), ACCR = a (qc qr)^e */
+    double auto_a, auto_qc_exp, auto_nc_exp, accr_a, accr_exp;
+    double m_r0;                   /* kg, mass of a new rain drop          */
+    double m_s0;                   /* kg, mass of a new snow particle      */
+    double m_i0;                   /* kg, mass of a nucleated crystal      */
+    double n_act;                  /* kg-1, number given to new cloud      */
+    /* Lin et al. 1983: IAUT = iaut_a exp(t_exp (T-T0)) (qi - q_i0); E_si = exp(t_exp (T-T0)) */
+    double iaut_a, ice_t_exp;
+    /* Bigg 1953 rain freezing: A' (K-1), B' (m-3 s-1) */
+    double bigg_a, bigg_b;
+    /* Cooper 1986 nucleation: n = min(a exp(b (T0-T)), max) per m3 */
+    double cooper_a, cooper_b, cooper_max;
+    /* snow and graupel intercepts, m-4 */
+    double N0_s, N0_g;
+    /* fall speed V(D) = a D^b (rho_0/rho)^1/2 for r, i, s, g; caps (m s-1) */
+    double fall_a[4], fall_b[4], v_max[4];
+    /* mean-diameter bounds 1/lambda, metres, for r, i, s, g */
+    double d_min[4], d_max[4];
+    int64_t capacity_points;       /* scratch sizing for compaction / surrogate */
+} casim_constants;
+
+/* Thresholds and solver controls. */
+typedef struct casim_thresholds {
+    double q_min;                  /* kg/kg: present if q >= q_min         */
+    double T_hom;                  /* K: homogeneous freezing below        */
+    double T_nuc;                  /* K: ice nucleation below              */
+    double q_i0;                   /* kg/kg: ice autoconversion threshold  */
+    int32_t newton_iters;          /* fixed Newton count of the adjustment */
+    int32_t reserved0;
+    double newton_rtol;            /* residual above which a point is flagged */
+    /* learned surrogate gating */
+    double sur_range_margin;       /* fraction of a feature's range added on each side */
+    double sur_maha_max;           /* squared Mahalanobis distance limit (0: from training) */
+    double sur_f_min;              /* limiter factor below which a point falls back */
+} casim_thresholds;
+
+/* One step's state.  All pointers except dz are device pointers.
+ *   in[14]  : T (K), p (Pa), rho (kg m-3), qv, qc, nc, qr, nr, qi, ni, qs, ns,
+ *             qg, ng (q in kg/kg, n in kg-1); read only.
+ *   dz      : HOST pointer to nlev layer thicknesses (m), read during the
+ *             call; the library keeps a device copy.
+ *   ld      : leading dimension (>= ncol) of every 3-D field.
+ *   tend[12]: dT, dqv, dqc, dnc, dqr, dnr, dqi, dni, dqs, dns, dqg, dng, per
+ *             second; written for every (k, c), c < ncol.
+ *   sfc[8]  : per column, mass of r, i, s, g reaching the surface during dt
+ *             (kg m-2), then their number (m-2); length >= ncol. */
+typedef struct casim_state {
+    const double *in[CASIM_NIN];
+    const double *dz;
+    int64_t ld;
+    double *tend[CASIM_NTEND];
+    double *sfc[CASIM_NSFC];
+} casim_state;
+
+/* Counters the step kernels raise on the device. */
+typedef struct casim_step_status {
+    int64_t newton_fail;    /* adjusted points with residual > newton_rtol */
+    int64_t nonfinite;      /* points with a non-finite tendency          */
+    int64_t fallback;       /* surrogate points that used the plain rates */
+    int64_t inferred;       /* surrogate points that used the network     */
+} casim_step_status;
+
+/* Fill *c / *t with the default published values.  Never fails on non-NULL. */
+int casim_default_constants(casim_constants *c);
+int casim_default_thresholds(casim_thresholds *t);
+
+/* Copy the constants to the device and allocate library scratch (Sec.
+ * III-B: constants and globals are moved to the device once, at
+ * initialisation).  May be called again to change constants or mode; it
+ * synchronises the device first.  Errors: EINVAL (NULL, bad mode/stages,
+ * non-positive physical constants), EHIP. */
+int casim_init(const casim_constants *c, const casim_thresholds *t);
+
+/* Enqueue one microphysics step over ncol columns of nlev levels on stream
+ * (Sec. III-B: one offloaded pass over all columns writing a source term per
+ * field).  Errors: ENOINIT, EINVAL (NULL pointer, ncol < 0, nlev outside
+ * 1..CASIM_MAX_NLEV, ld < ncol, dt not finite or <= 0, dz not finite or
+ * <= 0), ENOSURROGATE, ECAPACITY, EHIP.  ncol == 0 is a no-op. */
+int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream);
+
+/* Parent-model helper for multi-step runs: X += dt * tend for the 12
+ * prognostic fields of `s` (in[] is written through a cast: it must be
+ * writable memory), q and n clipped at 0.  Errors as casim_step. */
+int casim_apply_tendencies(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream);
+
+/* Synchronise `stream`, copy the device counters into *out and reset them.
+ * Errors: ENOINIT, EINVAL (NULL out), EHIP. */
+int casim_status(void *stream, casim_step_status *out);
+
+/* Free library-owned device memory (never caller memory).  Safe to call
+ * twice. */
+int casim_finalize(void);
+
+/* Static text for a code; for CASIM_EHIP, the last HIP error seen. */
+const char *casim_strerror(int code);
+
+/* Number of sedimentation substeps per category r, i, s, g that casim_step
+ * uses for this grid and dt: max(1, ceil(v_max dt / min dz)).  Host only. */
+int casim_nsub(const double *dz_host, int32_t nlev, double dt, int32_t nsub_out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

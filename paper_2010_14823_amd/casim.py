@@ -1,0 +1,215 @@
+"""ctypes binding of libcasim (include/casim.h): argument marshalling only.
+
+Every step of the microphysics runs in the HIP kernels of libcasim.so; this
+module only builds the C structs, takes device pointers and the current HIP
+stream from PyTorch tensors, and turns negative return codes into
+``CasimError``.  If the shared library has not been built, loading fails
+loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcasim.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "casim.h")
+
+MODE_FP64, MODE_FP32MIX, MODE_SURROGATE = 0, 1, 2
+STAGE_ADJUST, STAGE_SATADJ, STAGE_RATES, STAGE_SED, STAGE_ALL = 1, 2, 4, 8, 15
+NIN, NTEND, NSFC = 14, 12, 8
+IN_NAMES = ("T", "p", "rho", "qv", "qc", "nc", "qr", "nr", "qi", "ni", "qs", "ns", "qg", "ng")
+TEND_NAMES = ("dT", "dqv", "dqc", "dnc", "dqr", "dnr", "dqi", "dni", "dqs", "dns", "dqg", "dng")
+SFC_NAMES = ("Pr", "Pi", "Ps", "Pg", "Nr", "Ni", "Ns", "Ng")
+
+_d4 = ctypes.c_double * 4
+
+
+class Constants(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("stages", ctypes.c_int32), ("warm", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32)] + \
+        [(n, ctypes.c_double) for n in (
+            "R_d", "R_v", "cp", "L_v", "L_s", "T_0", "g", "rho_w", "rho_i", "rho_s", "rho_g",
+            "rho_0", "K_a", "Dv0", "Dv_exp", "esl_a", "esl_b", "esl_c", "esi_a", "esi_b", "esi_c",
+            "auto_a", "auto_qc_exp", "auto_nc_exp", "accr_a", "accr_exp", "m_r0", "m_s0", "m_i0",
+            "n_act", "iaut_a", "ice_t_exp", "bigg_a", "bigg_b", "cooper_a", "cooper_b",
+            "cooper_max", "N0_s", "N0_g")] + \
+        [("fall_a", _d4), ("fall_b", _d4), ("v_max", _d4), ("d_min", _d4), ("d_max", _d4),
+         ("capacity_points", ctypes.c_int64)]
+
+
+class Thresholds(ctypes.Structure):
+    _fields_ = [("q_min", ctypes.c_double), ("T_hom", ctypes.c_double), ("T_nuc", ctypes.c_double),
+                ("q_i0", ctypes.c_double), ("newton_iters", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("newton_rtol", ctypes.c_double),
+                ("sur_range_margin", ctypes.c_double), ("sur_maha_max", ctypes.c_double),
+                ("sur_f_min", ctypes.c_double)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p * NIN), ("dz", ctypes.POINTER(ctypes.c_double)),
+                ("ld", ctypes.c_int64), ("tend", ctypes.c_void_p * NTEND),
+                ("sfc", ctypes.c_void_p * NSFC)]
+
+
+class StepStatus(ctypes.Structure):
+    _fields_ = [("newton_fail", ctypes.c_int64), ("nonfinite", ctypes.c_int64),
+                ("fallback", ctypes.c_int64), ("inferred", ctypes.c_int64)]
+
+
+class CasimError(RuntimeError):
+    def __init__(self, code, func):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (func, strerror(code), code))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libcasim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcasim.so is not built: run python -m paper_2010_14823_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        sigs = {
+            "casim_default_constants": [ctypes.POINTER(Constants)],
+            "casim_default_thresholds": [ctypes.POINTER(Thresholds)],
+            "casim_init": [ctypes.POINTER(Constants), ctypes.POINTER(Thresholds)],
+            "casim_step": [ctypes.POINTER(State), i64, i32, dbl, vp],
+            "casim_apply_tendencies": [ctypes.POINTER(State), i64, i32, dbl, vp],
+            "casim_status": [vp, ctypes.POINTER(StepStatus)],
+            "casim_finalize": [],
+            "casim_nsub": [ctypes.POINTER(ctypes.c_double), i32, dbl, ctypes.POINTER(ctypes.c_int32)],
+        }
+        for name, args in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.casim_strerror.argtypes = [ctypes.c_int]
+        L.casim_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def header_functions(path: str = HEADER):
+    """Names of the functions include/casim.h declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(casim_[a-z0-9_]+)\s*\(", text)))
+
+
+def strerror(code: int) -> str:
+    return lib().casim_strerror(int(code)).decode()
+
+
+def _check(rc: int, func: str):
+    if rc != 0:
+        raise CasimError(rc, func)
+
+
+def default_constants(**overrides) -> Constants:
+    c = Constants()
+    _check(lib().casim_default_constants(ctypes.byref(c)), "casim_default_constants")
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c
+
+
+def default_thresholds(**overrides) -> Thresholds:
+    t = Thresholds()
+    _check(lib().casim_default_thresholds(ctypes.byref(t)), "casim_default_thresholds")
+    for k, v in overrides.items():
+        setattr(t, k, v)
+    return t
+
+
+def init(constants: Constants | None = None, thresholds: Thresholds | None = None):
+    c = constants if constants is not None else default_constants()
+    t = thresholds if thresholds is not None else default_thresholds()
+    _check(lib().casim_init(ctypes.byref(c), ctypes.byref(t)), "casim_init")
+
+
+def finalize():
+    _check(lib().casim_finalize(), "casim_finalize")
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_state(state, dz, tend, sfc, ld: int | None = None) -> State:
+    """Build a casim_state from device tensors.
+
+    ``state``: float64 cuda tensor (14, nlev, ld); ``tend``: (12, nlev, ld);
+    ``sfc``: (8, >= ncol); ``dz``: host sequence of nlev thicknesses (m).
+    """
+    import numpy as np
+    st = State()
+    for f in range(NIN):
+        st.in_[f] = state[f].data_ptr()
+    for f in range(NTEND):
+        st.tend[f] = tend[f].data_ptr()
+    for f in range(NSFC):
+        st.sfc[f] = sfc[f].data_ptr()
+    dzh = np.ascontiguousarray(dz, dtype=np.float64)
+    st._dz_keep = dzh
+    st.dz = dzh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st.ld = int(ld if ld is not None else state.shape[-1])
+    return st
+
+
+def _check_tensors(state, tend, sfc, ncol):
+    import torch
+    for name, t, lead in (("state", state, NIN), ("tend", tend, NTEND), ("sfc", sfc, NSFC)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous float64 cuda tensor" % name)
+        if t.shape[0] != lead:
+            raise ValueError("%s must have %d fields" % (name, lead))
+    if state.shape[1:] != tend.shape[1:]:
+        raise ValueError("state and tend must share (nlev, ld)")
+    if sfc.shape[-1] < ncol:
+        raise ValueError("sfc is shorter than ncol")
+
+
+def step(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
+    """Enqueue casim_step on the current (or given) stream."""
+    nlev, ld = state.shape[1], state.shape[2]
+    ncol = ld if ncol is None else int(ncol)
+    _check_tensors(state, tend, sfc, ncol)
+    st = make_state(state, dz, tend, sfc, ld)
+    _check(lib().casim_step(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
+           "casim_step")
+
+
+def apply_tendencies(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
+    nlev, ld = state.shape[1], state.shape[2]
+    ncol = ld if ncol is None else int(ncol)
+    _check_tensors(state, tend, sfc, ncol)
+    st = make_state(state, dz, tend, sfc, ld)
+    _check(lib().casim_apply_tendencies(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
+           "casim_apply_tendencies")
+
+
+def status(stream=None) -> dict:
+    s = StepStatus()
+    _check(lib().casim_status(_stream_handle(stream), ctypes.byref(s)), "casim_status")
+    return {"newton_fail": s.newton_fail, "nonfinite": s.nonfinite,
+            "fallback": s.fallback, "inferred": s.inferred}
+
+
+def nsub(dz, dt: float):
+    import numpy as np
+    dzh = np.ascontiguousarray(dz, dtype=np.float64)
+    out = (ctypes.c_int32 * 4)()
+    _check(lib().casim_nsub(dzh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(dzh),
+                            float(dt), out), "casim_nsub")
+    return list(out)

@@ -1,0 +1,60 @@
+"""Host-side checks of the C ABI: the library loads, exports what its header
+declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from paper_2010_14823_amd import casim, synth
+
+
+@pytest.fixture(scope="module")
+def L():
+    return casim.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = casim.header_functions()
+    assert "casim_init" in names and "casim_step" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_defaults(L):
+    c = casim.default_constants()
+    t = casim.default_thresholds()
+    assert c.mode == casim.MODE_FP64 and c.stages == casim.STAGE_ALL
+    assert c.R_d == 287.04 and c.cp == 1005.0 and c.L_s > c.L_v
+    assert list(c.v_max) == [10.0, 3.0, 3.0, 20.0]
+    assert t.newton_iters == 5 and t.q_min == 1e-12 and t.T_hom == 233.15
+
+
+def test_errors_before_init(L):
+    assert L.casim_step(None, 1, 1, 1.0, None) == -2
+    assert L.casim_status(None, ctypes.byref(casim.StepStatus())) == -2
+    assert L.casim_apply_tendencies(None, 1, 1, 1.0, None) == -2
+    assert L.casim_init(None, None) == -1
+    c = casim.default_constants(mode=7)
+    t = casim.default_thresholds()
+    assert L.casim_init(ctypes.byref(c), ctypes.byref(t)) == -1
+    c = casim.default_constants(cp=-1.0)
+    assert L.casim_init(ctypes.byref(c), ctypes.byref(t)) == -1
+    c = casim.default_constants()
+    t = casim.default_thresholds(newton_iters=-3)
+    assert L.casim_init(ctypes.byref(c), ctypes.byref(t)) == -1
+    for code in (0, -1, -2, -3, -4, -5, -99):
+        assert isinstance(casim.strerror(code), str)
+    assert L.casim_finalize() == 0
+
+
+def test_nsub_host_logic(L, oracle_lib):
+    for nlev in (1, 60, 100, 120):
+        dz, _ = synth.vertical_grid(nlev)
+        for dt in (0.5, 2.0, 10.0):
+            assert casim.nsub(dz, dt) == oracle_lib.nsub(dz, dt)
+    dz = np.array([10.0, -1.0])
+    with pytest.raises(casim.CasimError):
+        casim.nsub(dz, 2.0)
+    with pytest.raises(casim.CasimError):
+        casim.nsub(np.array([10.0]), math.nan)

@@ -1,0 +1,163 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+FP64 contract: for each of the 12 tendency fields and the 8 surface fields,
+max|gpu - oracle| / max|oracle| <= 1e-12 (normwise; pointwise relative error
+is ill-conditioned where q_v - q_sat cancels).  Clear subsaturated columns
+must come out as exact zeros.
+"""
+import numpy as np
+import pytest
+
+from paper_2010_14823_amd import synth
+from util import SFC, TEND, config_state, field_errors, oracle_steps, run_gpu
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _assert_parity(oracle_lib, st, dz, dt, tol=TOL, tag="", **kw):
+    okw = {k: v for k, v in kw.items() if k in ("stages", "warm", "newton_iters")}
+    tg, sg, status, _ = run_gpu(st, dz, dt, **kw)
+    ncol = kw.get("ncol") or st.shape[2]
+    to, so, fails = oracle_lib.step(st[:, :, :ncol], dz, dt, return_fails=True, **okw)
+    errs = field_errors(tg[:, :, :ncol], sg[:, :ncol], to, so)
+    print(tag, {k: float("%.3g" % v) for k, v in errs.items()}, status, "oracle newton fails", fails, flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, bad
+    assert status["nonfinite"] == 0
+    assert status["newton_fail"] == fails
+    return tg, sg, to, so
+
+
+def test_c0_full(oracle_lib):
+    cfg, st, dz, _ = config_state("c0")
+    _assert_parity(oracle_lib, st, dz, cfg.dt, tag="c0")
+
+
+def test_c1_full_and_clear_columns_zero(oracle_lib):
+    cfg, st, dz, cols = config_state("c1")
+    tg, sg, to, so = _assert_parity(oracle_lib, st, dz, cfg.dt, tag="c1")
+    clear = ~synth.cloud_mask(cfg)[cols]
+    assert clear.sum() > 1000
+    assert np.all(tg[:, :, clear] == 0.0)
+    assert np.all(sg[:, clear] == 0.0)
+
+
+@pytest.mark.parametrize("key", ["c2", "c3", "c4"])
+def test_large_config_row_subset(oracle_lib, key):
+    # columns are independent: a subset of grid rows is the full computation
+    cfg = synth.CONFIGS[key]
+    rows = list(range(0, cfg.ny, cfg.ny // 24))[:24]
+    cfg, st, dz, cols = config_state(key, rows)
+    _assert_parity(oracle_lib, st, dz, cfg.dt, tag=key)
+
+
+def test_ragged_tail_and_padding(oracle_lib):
+    cfg, st, dz, _ = config_state("c0")
+    # 50 columns in a leading dimension of 77: padding holds NaN and must stay unread/unwritten
+    tg, sg, status, _ = run_gpu(st, dz, cfg.dt, ncol=50, ld=77)
+    to, so = oracle_lib.step(st[:, :, :50], dz, cfg.dt)
+    errs = field_errors(tg[:, :, :50], sg[:, :50], to, so)
+    assert max(errs.values()) <= TOL, errs
+    assert np.all(tg[:, :, 50:] == -7.0) and np.all(sg[:, 50:] == -7.0)
+    assert status["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("ncol", [1, 63, 65, 129])
+def test_odd_column_counts(oracle_lib, ncol):
+    cfg = synth.Config("odd", 16, 9, 60, 21, 0.5)
+    f, dz, _ = synth.generate(cfg)
+    st = synth.stack(f)[:, :, :ncol].copy()
+    _assert_parity(oracle_lib, st, dz, 2.0, tag="ncol%d" % ncol)
+
+
+def test_single_level_and_zero_columns(oracle_lib):
+    cfg, st, dz, _ = config_state("c0")
+    one = st[:, 30:31, :].copy()
+    _assert_parity(oracle_lib, one, dz[30:31], 2.0, tag="nlev1")
+    import torch
+    from paper_2010_14823_amd import casim
+    casim.init()
+    dev = torch.zeros((14, 3, 4), dtype=torch.float64, device="cuda")
+    tend = torch.full((12, 3, 4), -1.0, dtype=torch.float64, device="cuda")
+    sfc = torch.full((8, 4), -1.0, dtype=torch.float64, device="cuda")
+    casim.step(dev, [10.0, 10.0, 10.0], 2.0, tend, sfc, ncol=0)
+    torch.cuda.synchronize()
+    assert torch.all(tend == -1.0)
+
+
+@pytest.mark.parametrize("dt", [0.5, 10.0])
+def test_many_substeps(oracle_lib, dt):
+    cfg = synth.Config("deep120", 32, 4, 120, 5, 0.5, deep=True)
+    f, dz, _ = synth.generate(cfg)
+    st = synth.stack(f)
+    ns = oracle_lib.nsub(dz, dt)
+    print("nsub", ns)
+    _assert_parity(oracle_lib, st, dz, dt, tag="dt%g" % dt)
+
+
+@pytest.mark.parametrize("stages", [1, 2, 3, 4, 8, 7, 12])
+def test_stage_subsets(oracle_lib, stages):
+    cfg, st, dz, _ = config_state("c0")
+    _assert_parity(oracle_lib, st, dz, cfg.dt, stages=stages, tag="stages%d" % stages)
+
+
+def test_warm_configuration(oracle_lib):
+    cfg, st, dz, _ = config_state("c0")
+    tg, sg, to, so = _assert_parity(oracle_lib, st, dz, cfg.dt, warm=1, tag="warm")
+    for j in range(6, 12):
+        assert np.all(tg[j] == 0.0)
+
+
+def test_newton_failure_flag(oracle_lib):
+    cfg, st, dz, _ = config_state("c0")
+    tg, sg, status, _ = run_gpu(st, dz, cfg.dt, newton_iters=1)
+    to, so, fails = oracle_lib.step(st, dz, cfg.dt, newton_iters=1, return_fails=True)
+    assert fails > 0
+    assert status["newton_fail"] == fails
+    errs = field_errors(tg, sg, to, so)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_deterministic(oracle_lib):
+    cfg, st, dz, _ = config_state("c0")
+    a = run_gpu(st, dz, cfg.dt)
+    b = run_gpu(st, dz, cfg.dt)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_nonfinite_input_counted(oracle_lib):
+    cfg, st, dz, _ = config_state("c0")
+    bad = st.copy()
+    bad[4, 10, 3] = np.inf          # one infinite cloud mass
+    tg, sg, status, _ = run_gpu(bad, dz, cfg.dt)
+    assert status["nonfinite"] >= 1
+
+
+def test_multistep_apply_matches_oracle(oracle_lib):
+    cfg, st, dz, _ = config_state("c0")
+    tg, sg, status, state_after = run_gpu(st, dz, cfg.dt, steps=4)
+    to, so = oracle_steps(oracle_lib, st, dz, cfg.dt, steps=4)
+    errs = field_errors(tg, sg, to, so)
+    print("4 steps", errs)
+    assert max(errs.values()) <= 1e-10, errs
+    # non-negativity of every q and n after the parent-model update
+    assert np.all(state_after[3:] >= 0.0)
+
+
+def test_argument_errors_on_device():
+    import torch
+    from paper_2010_14823_amd import casim
+    casim.init()
+    dev = torch.zeros((14, 3, 8), dtype=torch.float64, device="cuda")
+    tend = torch.zeros((12, 3, 8), dtype=torch.float64, device="cuda")
+    sfc = torch.zeros((8, 8), dtype=torch.float64, device="cuda")
+    dz = [10.0, 10.0, 10.0]
+    for kw in ({"dt": 0.0}, {"dt": float("nan")}, {"dz": [10.0, 0.0, 10.0]}, {"dz": [10.0, float("inf"), 1.0]}):
+        a = {"dt": 2.0, "dz": dz}; a.update(kw)
+        with pytest.raises(casim.CasimError) as e:
+            casim.step(dev, a["dz"], a["dt"], tend, sfc)
+        assert e.value.code == -1
+    st = casim.make_state(dev, dz, tend, sfc, ld=4)      # ld < ncol
+    assert casim.lib().casim_step(st, 8, 3, 2.0, None) == -1
+    assert casim.lib().casim_step(st, 2, 600, 2.0, None) == -1
