@@ -59,6 +59,23 @@ def cpu_baseline(st, dz, dt, budget_s=12.0):
                       % (st.shape[2], st.shape[1], len(times), t)}
 
 
+def copy_probe(torch, nbytes=2 << 30, reps=5):
+    """Achieved bandwidth of a plain 2 GiB device-to-device copy (read + write)."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms, "GBps": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +84,9 @@ def main():
     ap.add_argument("--config", default="c1")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32mix"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="also time a plain device-to-device copy of 2 GiB (bandwidth reference "
+                         "and scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the column step needs no exchange between GPUs "
@@ -77,6 +97,8 @@ def main():
     from paper_2010_14823_amd import casim, synth
 
     cfg = synth.CONFIGS[args.config]
+    print("bench: generating %s (%d columns x %d levels)" % (cfg.name, cfg.ncol, cfg.nlev),
+          file=sys.stderr, flush=True)
     fields, dz, cols = synth.generate(cfg)
     st = synth.stack(fields)
     mask = synth.cloud_mask(cfg)
@@ -133,6 +155,9 @@ def main():
                      "kernel": "sweep_kernel", "kernel_ms": kern_ms, "algorithmic_bytes": alg},
         "status": status,
     }
+    print("bench: %.4f ms/step on the GPU" % ms_per_step, file=sys.stderr, flush=True)
+    if args.with_copy:
+        line["copy_probe"] = copy_probe(torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(st, dz, cfg.dt)
     print(json.dumps(line), flush=True)

@@ -59,6 +59,11 @@ extern "C" {
 #define CASIM_STAGE_SED    8    /* sedimentation of rain, ice, snow, graupel */
 #define CASIM_STAGE_ALL    15
 
+/* casim_constants.flags: use the kernel that reads every constant at run time
+ * even when the constants equal the defaults (the defaults are otherwise
+ * compiled into a specialised kernel). */
+#define CASIM_FLAG_GENERIC 1
+
 #define CASIM_MAX_NLEV     512  /* largest number of levels per column     */
 #define CASIM_NIN          14
 #define CASIM_NTEND        12
@@ -72,7 +77,7 @@ typedef struct casim_constants {
     int32_t mode;                  /* CASIM_MODE_*                          */
     int32_t stages;                /* CASIM_STAGE_* bits                    */
     int32_t warm;                  /* 1: warm configuration (no ice), Sec. II */
-    int32_t reserved0;
+    int32_t flags;                 /* CASIM_FLAG_* bits                     */
     /* gas and phase change */
     double R_d, R_v, cp, L_v, L_s;               /* J kg-1 K-1, J kg-1      */
     double T_0, g;                                /* K, m s-2                */
@@ -181,6 +186,13 @@ const char *casim_strerror(int code);
 /* Number of sedimentation substeps per category r, i, s, g that casim_step
  * uses for this grid and dt: max(1, ceil(v_max dt / min dz)).  Host only. */
 int casim_nsub(const double *dz_host, int32_t nlev, double dt, int32_t nsub_out[4]);
+
+/* Diagnostics: evaluate the binary64 exponential and logarithm that the
+ * step kernels use internally, elementwise on n device values x (x > 0 for a
+ * meaningful log), into device arrays exp_out and log_out (either may be
+ * NULL).  Lets callers check their accuracy against a host library.
+ * Errors: EINVAL (NULL x, n < 0), EHIP. */
+int casim_debug_math(const double *x, int64_t n, double *exp_out, double *log_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "casim.h")
 
 MODE_FP64, MODE_FP32MIX, MODE_SURROGATE = 0, 1, 2
 STAGE_ADJUST, STAGE_SATADJ, STAGE_RATES, STAGE_SED, STAGE_ALL = 1, 2, 4, 8, 15
+FLAG_GENERIC = 1
 NIN, NTEND, NSFC = 14, 12, 8
 IN_NAMES = ("T", "p", "rho", "qv", "qc", "nc", "qr", "nr", "qi", "ni", "qs", "ns", "qg", "ng")
 TEND_NAMES = ("dT", "dqv", "dqc", "dnc", "dqr", "dnr", "dqi", "dni", "dqs", "dns", "dqg", "dng")
@@ -28,7 +29,7 @@ _d4 = ctypes.c_double * 4
 
 class Constants(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("stages", ctypes.c_int32), ("warm", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32)] + \
+                ("flags", ctypes.c_int32)] + \
         [(n, ctypes.c_double) for n in (
             "R_d", "R_v", "cp", "L_v", "L_s", "T_0", "g", "rho_w", "rho_i", "rho_s", "rho_g",
             "rho_0", "K_a", "Dv0", "Dv_exp", "esl_a", "esl_b", "esl_c", "esi_a", "esi_b", "esi_c",
@@ -84,6 +85,7 @@ def lib():
             "casim_status": [vp, ctypes.POINTER(StepStatus)],
             "casim_finalize": [],
             "casim_nsub": [ctypes.POINTER(ctypes.c_double), i32, dbl, ctypes.POINTER(ctypes.c_int32)],
+            "casim_debug_math": [vp, i64, vp, vp, vp],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -213,3 +215,13 @@ def nsub(dz, dt: float):
     _check(lib().casim_nsub(dzh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(dzh),
                             float(dt), out), "casim_nsub")
     return list(out)
+
+
+def debug_math(x, stream=None):
+    """(exp(x), log(x)) evaluated by the library's internal binary64 routines."""
+    import torch
+    e = torch.empty_like(x)
+    l = torch.empty_like(x)
+    _check(lib().casim_debug_math(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(e.data_ptr()),
+                                  ctypes.c_void_p(l.data_ptr()), _stream_handle(stream)), "casim_debug_math")
+    return e, l

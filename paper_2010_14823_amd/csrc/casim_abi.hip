@@ -18,6 +18,7 @@ struct Context {
     casim_constants c{};
     casim_thresholds t{};
     DevParams P{};
+    bool fast = false;                      // defaults compiled into the kernels
     double *d_dz = nullptr;                 // device copy of the vertical grid
     std::vector<double> h_dz;               // what d_dz holds
     unsigned long long *d_status = nullptr; // 4 counters
@@ -59,61 +60,38 @@ int validate_constants(const casim_constants *c, const casim_thresholds *t) {
     return CASIM_OK;
 }
 
-DevParams derive(const casim_constants &c, const casim_thresholds &t) {
-    const double pi = 3.14159265358979323846;
-    DevParams P{};
-    P.mode = c.mode;
-    P.stages = c.stages;
-    P.warm = c.warm ? 1 : 0;
-    P.newton_iters = t.newton_iters;
-    P.eps = c.R_d / c.R_v;
-    P.one_m_eps = 1.0 - P.eps;
-    P.cp = c.cp;
-    P.inv_cp = 1.0 / c.cp;
-    P.L_v = c.L_v;
-    P.L_s = c.L_s;
-    P.L_f = c.L_s - c.L_v;
-    P.R_v = c.R_v;
-    P.T_0 = c.T_0;
-    P.T_hom = t.T_hom;
-    P.T_nuc = t.T_nuc;
-    P.rho_0 = c.rho_0;
-    P.K_a = c.K_a;
-    P.Dv0 = c.Dv0;
-    P.Dv_exp = c.Dv_exp;
-    P.esl_a = c.esl_a; P.esl_b = c.esl_b; P.esl_c = c.esl_c; P.esl_bc = c.esl_b * c.esl_c;
-    P.esi_a = c.esi_a; P.esi_b = c.esi_b; P.esi_c = c.esi_c;
-    P.auto_a = c.auto_a; P.auto_qc_exp = c.auto_qc_exp; P.auto_nc_exp = c.auto_nc_exp;
-    P.accr_a = c.accr_a; P.accr_exp = c.accr_exp;
-    P.inv_m_r0 = 1.0 / c.m_r0;
-    P.inv_m_s0 = 1.0 / c.m_s0;
-    P.m_i0 = c.m_i0;
-    P.n_act = c.n_act;
-    P.iaut_a = c.iaut_a;
-    P.ice_t_exp = c.ice_t_exp;
-    P.q_i0 = t.q_i0;
-    P.bigg_a = c.bigg_a;
-    P.frzr_coef = 20.0 * pi * pi * c.bigg_b * c.rho_w;
-    P.cooper_a = c.cooper_a; P.cooper_b = c.cooper_b; P.cooper_max = c.cooper_max;
-    P.N0_s = c.N0_s;
-    P.N0_g = c.N0_g;
-    P.coll_s = 0.25 * pi * c.fall_a[2] * c.N0_s * tgamma(3.0 + c.fall_b[2]);
-    P.coll_g = 0.25 * pi * c.fall_a[3] * c.N0_g * tgamma(3.0 + c.fall_b[3]);
-    P.lam_coef[0] = pi * c.rho_w;
-    P.lam_coef[1] = pi * c.rho_i;
-    P.lam_coef[2] = pi * c.rho_s * c.N0_s;
-    P.lam_coef[3] = pi * c.rho_g * c.N0_g;
+GammaTable gamma_table(const casim_constants &c) {
+    GammaTable gm{};
     for (int j = 0; j < 4; ++j) {
-        P.lam_lo[j] = 1.0 / c.d_max[j];
-        P.lam_hi[j] = 1.0 / c.d_min[j];
-        P.fall_b[j] = c.fall_b[j];
-        P.vq_coef[j] = c.fall_a[j] * tgamma(4.0 + c.fall_b[j]) / 6.0;
-        P.vn_coef[j] = c.fall_a[j] * tgamma(1.0 + c.fall_b[j]);
-        P.v_max[j] = c.v_max[j];
+        gm.g4[j] = tgamma(4.0 + c.fall_b[j]);
+        gm.g1[j] = tgamma(1.0 + c.fall_b[j]);
     }
-    P.q_min = t.q_min;
-    P.newton_rtol = t.newton_rtol;
-    return P;
+    gm.g3s = tgamma(3.0 + c.fall_b[2]);
+    gm.g3g = tgamma(3.0 + c.fall_b[3]);
+    return gm;
+}
+
+bool close_rel(double a, double b) { return fabs(a - b) <= 1e-14 * fabs(b); }
+
+// The compiled-in parameters serve a constant set equal to the defaults in
+// every physical value (mode, stages, warm, flags, capacity and the Newton
+// count stay run-time choices).
+bool defaults_apply(const casim_constants &c, const casim_thresholds &t) {
+    if (c.flags & CASIM_FLAG_GENERIC) return false;
+    casim_constants cc = c;
+    const casim_constants dc = default_constants();
+    cc.mode = dc.mode; cc.stages = dc.stages; cc.warm = dc.warm; cc.flags = dc.flags;
+    cc.capacity_points = dc.capacity_points;
+    if (memcmp(&cc, &dc, sizeof cc) != 0) return false;
+    const casim_thresholds dt = default_thresholds();
+    if (t.q_min != dt.q_min || t.T_hom != dt.T_hom || t.T_nuc != dt.T_nuc || t.q_i0 != dt.q_i0 ||
+        t.newton_rtol != dt.newton_rtol)
+        return false;
+    const GammaTable gm = gamma_table(dc);
+    for (int j = 0; j < 4; ++j)
+        if (!close_rel(kDefaultGamma.g4[j], gm.g4[j]) || !close_rel(kDefaultGamma.g1[j], gm.g1[j]))
+            return false;
+    return close_rel(kDefaultGamma.g3s, gm.g3s) && close_rel(kDefaultGamma.g3g, gm.g3g);
 }
 
 void nsub_of(const casim_constants &c, const double *dz, int nlev, double dt, int32_t out[4]) {
@@ -162,6 +140,10 @@ int fill_args(const casim_state *s, int64_t ncol, int32_t nlev, double dt, Sweep
     a.nlev = nlev;
     a.dt = dt;
     a.status = g.d_status;
+    a.stages = g.c.stages;
+    a.warm = g.c.warm ? 1 : 0;
+    a.newton_iters = g.t.newton_iters;
+    a.mode = g.c.mode;
     return CASIM_OK;
 }
 
@@ -171,49 +153,13 @@ extern "C" {
 
 int casim_default_constants(casim_constants *c) {
     if (!c) return CASIM_EINVAL;
-    memset(c, 0, sizeof *c);
-    c->mode = CASIM_MODE_FP64;
-    c->stages = CASIM_STAGE_ALL;
-    c->warm = 0;
-    c->R_d = 287.04; c->R_v = 461.5; c->cp = 1005.0; c->L_v = 2.501e6; c->L_s = 2.834e6;
-    c->T_0 = 273.15; c->g = 9.80665;
-    c->rho_w = 1000.0; c->rho_i = 500.0; c->rho_s = 100.0; c->rho_g = 400.0; c->rho_0 = 1.225;
-    c->K_a = 2.4e-2; c->Dv0 = 2.11e-5; c->Dv_exp = 1.94;
-    c->esl_a = 611.2; c->esl_b = 17.67; c->esl_c = 243.5;       // Bolton (1980)
-    c->esi_a = 611.15; c->esi_b = 22.452; c->esi_c = 272.55;    // Buck (1981), ice
-    c->auto_a = 1350.0; c->auto_qc_exp = 2.47; c->auto_nc_exp = -1.79;   // KK2000
-    c->accr_a = 67.0; c->accr_exp = 1.15;
-    c->m_r0 = 6.545e-11;
-    c->m_s0 = 3.14159265358979323846 / 6.0 * 100.0 * 1e-12;   // (pi/6) rho_s (100 um)^3
-    c->m_i0 = 1e-12;
-    c->n_act = 1e8;
-    c->iaut_a = 1e-3; c->ice_t_exp = 0.025;                    // Lin et al. (1983)
-    c->bigg_a = 0.66; c->bigg_b = 100.0;                       // Bigg (1953)
-    c->cooper_a = 5.0; c->cooper_b = 0.304; c->cooper_max = 5e5; // Cooper (1986)
-    c->N0_s = 3e6; c->N0_g = 4e6;
-    const double fa[4] = {842.0, 700.0, 11.72, 19.3}, fb[4] = {0.8, 1.0, 0.41, 0.37};
-    const double vm[4] = {10.0, 3.0, 3.0, 20.0};
-    const double dmin[4] = {2e-5, 1e-6, 1e-5, 1e-5}, dmax[4] = {5e-3, 1e-3, 1e-2, 1e-2};
-    for (int j = 0; j < 4; ++j) {
-        c->fall_a[j] = fa[j]; c->fall_b[j] = fb[j]; c->v_max[j] = vm[j];
-        c->d_min[j] = dmin[j]; c->d_max[j] = dmax[j];
-    }
-    c->capacity_points = 0;
+    *c = default_constants();
     return CASIM_OK;
 }
 
 int casim_default_thresholds(casim_thresholds *t) {
     if (!t) return CASIM_EINVAL;
-    memset(t, 0, sizeof *t);
-    t->q_min = 1e-12;
-    t->T_hom = 233.15;
-    t->T_nuc = 268.15;
-    t->q_i0 = 1e-4;
-    t->newton_iters = 5;
-    t->newton_rtol = 1e-10;
-    t->sur_range_margin = 0.05;
-    t->sur_maha_max = 0.0;
-    t->sur_f_min = 0.5;
+    *t = default_thresholds();
     return CASIM_OK;
 }
 
@@ -232,7 +178,8 @@ int casim_init(const casim_constants *c, const casim_thresholds *t) {
     }
     g.c = *c;
     g.t = *t;
-    g.P = derive(*c, *t);
+    g.P = derive(*c, *t, gamma_table(*c));
+    g.fast = defaults_apply(*c, *t);
     g.init = true;
     return CASIM_OK;
 }
@@ -242,8 +189,7 @@ int casim_nsub(const double *dz_host, int32_t nlev, double dt, int32_t nsub_out[
         return CASIM_EINVAL;
     for (int k = 0; k < nlev; ++k)
         if (!pos_finite(dz_host[k])) return CASIM_EINVAL;
-    casim_constants c;
-    if (g.init) c = g.c; else casim_default_constants(&c);
+    const casim_constants c = g.init ? g.c : default_constants();
     nsub_of(c, dz_host, nlev, dt, nsub_out);
     return CASIM_OK;
 }
@@ -257,7 +203,7 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
         if (!s->sfc[f]) return CASIM_EINVAL;
     for (int k = 0; k < nlev; ++k)
         if (!pos_finite(s->dz[k])) return CASIM_EINVAL;
-    if (g.P.mode == CASIM_MODE_SURROGATE) return CASIM_ENOSURROGATE;
+    if (g.c.mode == CASIM_MODE_SURROGATE) return CASIM_ENOSURROGATE;
     SweepArgs a{};
     fill_args(s, ncol, nlev, dt, a);
     nsub_of(g.c, s->dz, nlev, dt, a.nsub);
@@ -270,7 +216,7 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
     if (slot > kMaxCarrySlots) return CASIM_ECAPACITY;
     rc = upload_dz(s->dz, nlev);
     if (rc) return rc;
-    HIP_TRY(launch_sweep(g.P, a, (hipStream_t)stream));
+    HIP_TRY(launch_sweep(g.P, g.fast, a, (hipStream_t)stream));
     return CASIM_OK;
 }
 
@@ -307,6 +253,13 @@ int casim_finalize(void) {
     g.h_dz.clear();
     g.init = false;
     g.device = -1;
+    return CASIM_OK;
+}
+
+int casim_debug_math(const double *x, int64_t n, double *exp_out, double *log_out, void *stream) {
+    if (!x || n < 0) return CASIM_EINVAL;
+    if (n == 0) return CASIM_OK;
+    HIP_TRY(launch_math(x, n, exp_out, log_out, (hipStream_t)stream));
     return CASIM_OK;
 }
 

@@ -6,20 +6,21 @@
 #include <stdint.h>
 
 #include "casim.h"
+#include "casim_defaults.h"
 
 namespace casim {
 
-constexpr int kWave = 64;            // CDNA wavefront width: one column per lane
+constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxCarrySlots = 64;   // 2 moments x sum of substeps over r,i,s,g
 
-// Device copy of the scheme's constants, with every derived quantity the
-// kernels need folded in at initialisation (no Gamma function or division of
-// constants in the sweep).  Passed by value as a kernel argument.
+// The scheme's constants with every derived quantity folded in, so the
+// sweep evaluates no Gamma function, logarithm of a constant or division of
+// constants.  Built by derive(); for the default constants it is a compile
+// time constant of the specialised kernels.
 struct DevParams {
-    int32_t mode, stages, warm, newton_iters;
     double eps, one_m_eps, cp, inv_cp, L_v, L_s, L_f, R_v, T_0, T_hom, T_nuc;
     double rho_0, K_a, Dv0, Dv_exp;
-    double esl_a, esl_b, esl_c, esl_bc;   // bc = b*c, slope numerator of the Newton derivative
+    double esl_a, esl_b, esl_c, esl_bc;   // bc = b*c: slope numerator of the Newton derivative
     double esi_a, esi_b, esi_c;
     double auto_a, auto_qc_exp, auto_nc_exp, accr_a, accr_exp;
     double inv_m_r0, inv_m_s0, m_i0, n_act;
@@ -28,11 +29,73 @@ struct DevParams {
     double cooper_a, cooper_b, cooper_max;
     double N0_s, N0_g;
     double coll_s, coll_g;                // (pi/4) a N0 Gamma(3+b) for snow, graupel
-    double lam_coef[4];                   // pi rho_w, pi rho_i, pi rho_s N0_s, pi rho_g N0_g
-    double lam_lo[4], lam_hi[4];          // 1/d_max, 1/d_min
+    double coll_exp_s, coll_exp_g;        // -(3 + b)
+    double ln_lam_coef[4];                // ln(pi rho_w), ln(pi rho_i), ln(pi rho_s N0_s), ln(pi rho_g N0_g)
+    double ln_lam_lo[4], ln_lam_hi[4];    // ln(1/d_max), ln(1/d_min)
     double fall_b[4], vq_coef[4], vn_coef[4], v_max[4];  // a Gamma(4+b)/6, a Gamma(1+b)
     double q_min, newton_rtol;
+    double ln_1e6;                        // ln(1e-6): kg-1 -> cm-3 factor in log space
+    double two_pi;
 };
+
+constexpr DevParams derive(const casim_constants &c, const casim_thresholds &t, const GammaTable &gm) {
+    DevParams P{};
+    P.eps = c.R_d / c.R_v;
+    P.one_m_eps = 1.0 - P.eps;
+    P.cp = c.cp;
+    P.inv_cp = 1.0 / c.cp;
+    P.L_v = c.L_v;
+    P.L_s = c.L_s;
+    P.L_f = c.L_s - c.L_v;
+    P.R_v = c.R_v;
+    P.T_0 = c.T_0;
+    P.T_hom = t.T_hom;
+    P.T_nuc = t.T_nuc;
+    P.rho_0 = c.rho_0;
+    P.K_a = c.K_a;
+    P.Dv0 = c.Dv0;
+    P.Dv_exp = c.Dv_exp;
+    P.esl_a = c.esl_a; P.esl_b = c.esl_b; P.esl_c = c.esl_c; P.esl_bc = c.esl_b * c.esl_c;
+    P.esi_a = c.esi_a; P.esi_b = c.esi_b; P.esi_c = c.esi_c;
+    P.auto_a = c.auto_a; P.auto_qc_exp = c.auto_qc_exp; P.auto_nc_exp = c.auto_nc_exp;
+    P.accr_a = c.accr_a; P.accr_exp = c.accr_exp;
+    P.inv_m_r0 = 1.0 / c.m_r0;
+    P.inv_m_s0 = 1.0 / c.m_s0;
+    P.m_i0 = c.m_i0;
+    P.n_act = c.n_act;
+    P.iaut_a = c.iaut_a;
+    P.ice_t_exp = c.ice_t_exp;
+    P.q_i0 = t.q_i0;
+    P.bigg_a = c.bigg_a;
+    P.frzr_coef = 20.0 * kPi * kPi * c.bigg_b * c.rho_w;
+    P.cooper_a = c.cooper_a; P.cooper_b = c.cooper_b; P.cooper_max = c.cooper_max;
+    P.N0_s = c.N0_s;
+    P.N0_g = c.N0_g;
+    P.coll_s = 0.25 * kPi * c.fall_a[2] * c.N0_s * gm.g3s;
+    P.coll_g = 0.25 * kPi * c.fall_a[3] * c.N0_g * gm.g3g;
+    P.coll_exp_s = -(3.0 + c.fall_b[2]);
+    P.coll_exp_g = -(3.0 + c.fall_b[3]);
+    P.ln_lam_coef[0] = cx_log(kPi * c.rho_w);
+    P.ln_lam_coef[1] = cx_log(kPi * c.rho_i);
+    P.ln_lam_coef[2] = cx_log(kPi * c.rho_s * c.N0_s);
+    P.ln_lam_coef[3] = cx_log(kPi * c.rho_g * c.N0_g);
+    for (int j = 0; j < 4; ++j) {
+        P.ln_lam_lo[j] = -cx_log(c.d_max[j]);
+        P.ln_lam_hi[j] = -cx_log(c.d_min[j]);
+        P.fall_b[j] = c.fall_b[j];
+        P.vq_coef[j] = c.fall_a[j] * gm.g4[j] / 6.0;
+        P.vn_coef[j] = c.fall_a[j] * gm.g1[j];
+        P.v_max[j] = c.v_max[j];
+    }
+    P.q_min = t.q_min;
+    P.newton_rtol = t.newton_rtol;
+    P.ln_1e6 = cx_log(1e-6);
+    P.two_pi = 2.0 * kPi;
+    return P;
+}
+
+// Parameters of the default constant set, as a compile-time constant.
+constexpr DevParams kDefaultParams = derive(default_constants(), default_thresholds(), kDefaultGamma);
 
 struct SweepArgs {
     const double *in[CASIM_NIN];
@@ -41,12 +104,15 @@ struct SweepArgs {
     const double *dz;          // device, nlev
     int64_t ld, ncol;
     int32_t nlev, nsub[4], slot0[4], nslots;
+    int32_t stages, warm, newton_iters, mode;
     double dt;
     unsigned long long *status;   // device counters: newton_fail, nonfinite, fallback, inferred
 };
 
-// Launchers (casim_sweep.hip).  Return a hipError_t from the launch.
-hipError_t launch_sweep(const DevParams &P, const SweepArgs &a, hipStream_t stream);
+// Launchers (casim_sweep.hip).  `fast` selects the kernels compiled with
+// kDefaultParams.  Return the launch's hipError_t.
+hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream);
 hipError_t launch_apply(const SweepArgs &a, double dt, hipStream_t stream);
+hipError_t launch_math(const double *x, int64_t n, double *e, double *l, hipStream_t stream);
 
 }  // namespace casim

@@ -1,50 +1,62 @@
 // Column-sweep kernels of the bulk-microphysics step for gfx950.
 //
-// Mapping (the paper's Sec. III-B mapping of one column per GPU thread, kept
-// because columns are independent, Sec. II): one column per lane of a
-// 64-wide wavefront, the lane walking its column from the top level down.
-// At each level a lane
-//   1. reads the 8 fields that decide whether anything can happen there
+// Columns are independent (Sec. II of the CASIM port study); the paper maps
+// one column to one GPU thread (Sec. III-B).  Here a 64-wide wavefront holds
+// a tile of C columns x L = 64/C consecutive levels (lane = g*C + c: column c
+// of the wave's column block, level group g, g = 0 the top of the tile), and
+// walks its columns from the top level down in chunks of L levels.  C = 64
+// is the one-column-per-lane mapping; C = 16 or 32 gives domains with few
+// columns four or two times as many wavefronts.  Per chunk a wavefront
+//   1. reads the 8 fields that decide whether anything can happen at a point
 //      (T, p, q_v and the five condensate masses);
-//   2. takes part in a wavefront ballot: when no lane of the wave has
-//      condensate, supersaturation or sedimentation inflow at this level,
-//      the wave writes exact zeros and moves on (clear sky costs 8 loads and
-//      12 stores per point);
-//   3. otherwise reads the remaining 6 fields and runs clean-up, instant
-//      phase changes, saturation adjustment, the 12 process rates and the
-//      limiter in registers;
-//   4. advances sedimentation of rain, ice, snow and graupel for every
-//      substep at once: explicit upwind sedimentation with a static substep
-//      count needs, at level k and substep s, only the flux leaving level
-//      k+1 at substep s, so the fluxes of the level above are carried down
-//      in LDS, one slot per (category, moment, substep) and lane;
-//   5. writes the 12 tendencies (accumulated increment / dt).
-// The surface outputs are the fluxes leaving level 0, summed over substeps.
+//   2. votes: when no point of the chunk has condensate or supersaturation
+//      and no sedimentation flux enters it from above, the chunk's 12
+//      tendencies are exact zeros and the wavefront moves on (clear sky costs
+//      8 loads and 12 stores per point);
+//   3. reads the other 6 fields where something can happen, and runs clean-up,
+//      instant phase changes, saturation adjustment, the 12 process rates and
+//      the source limiter for all 64 points at once;
+//   4. sediments rain, ice, snow and graupel.  Explicit flux-form upwind with
+//      a static substep count couples level k at substep s only to the flux
+//      leaving level k+1 at substep s, so all substeps of a chunk are done in
+//      order with every level of the chunk in parallel: the flux from the
+//      level above comes from the lane C places lower (a cross-lane shuffle),
+//      and for the top level of the chunk from the previous chunk's bottom
+//      level, kept in LDS per (category, moment, substep, column);
+//   5. writes the tendencies (accumulated increment / dt).
+//
+// Slopes of the size distributions are handled in log space: lambda^b,
+// lambda^-7 etc. become exp(k ln lambda) and the mean-diameter clamp is a
+// clamp of ln lambda.
 //
 // Precision policy: MIX = false runs everything in binary64.  MIX = true
 // evaluates the 12 process rates and the fall speeds in binary32 and keeps
 // binary64 for saturation pressures, the saturation adjustment, the limiter
 // and apply, the sedimentation fluxes, level updates and surface sums.
 #include "casim_internal.h"
+#include "casim_math.h"
 
 namespace casim {
 
+__device__ constexpr DevParams kFastParams = kDefaultParams;
+
+template <bool FAST>
+__device__ __forceinline__ const DevParams &params(const DevParams &rt) {
+    if constexpr (FAST) return kFastParams;
+    else return rt;
+}
+
 template <class R> struct Mth;
 template <> struct Mth<double> {
-    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
-    static __device__ __forceinline__ double pow(double x, double y) { return ::pow(x, y); }
-    static __device__ __forceinline__ double cbrt(double x) { return ::cbrt(x); }
-    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double exp(double x) { return exp64(x); }
+    static __device__ __forceinline__ double log(double x) { return log64(x); }
     static __device__ __forceinline__ double fmin(double a, double b) { return ::fmin(a, b); }
-    static __device__ __forceinline__ double fmax(double a, double b) { return ::fmax(a, b); }
 };
 template <> struct Mth<float> {
-    static __device__ __forceinline__ float exp(float x) { return ::expf(x); }
-    static __device__ __forceinline__ float pow(float x, float y) { return ::powf(x, y); }
-    static __device__ __forceinline__ float cbrt(float x) { return ::cbrtf(x); }
-    static __device__ __forceinline__ float sqrt(float x) { return ::sqrtf(x); }
+    // hardware base-2 exponential and logarithm (v_exp_f32 / v_log_f32)
+    static __device__ __forceinline__ float exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+    static __device__ __forceinline__ float log(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
     static __device__ __forceinline__ float fmin(float a, float b) { return ::fminf(a, b); }
-    static __device__ __forceinline__ float fmax(float a, float b) { return ::fmaxf(a, b); }
 };
 
 template <class R>
@@ -55,13 +67,16 @@ struct Pt {
     double T, qv, qc, nc, qr, nr, qi, ni, qs, ns, qg, ng;
 };
 
+// Saturation vapour pressure a exp(b Tc / (Tc + c)), Tc = T - T0 (Bolton
+// 1980 over liquid, Buck 1981 over ice).  Always evaluated through the same
+// expression so a value computed once can be reused for the same T.
 __device__ __forceinline__ double esat_liq(const DevParams &P, double T) {
-    double Tc = T - P.T_0;
-    return P.esl_a * ::exp(P.esl_b * Tc / (Tc + P.esl_c));
+    const double Tc = T - P.T_0;
+    return P.esl_a * exp64(P.esl_b * Tc * (1.0 / (Tc + P.esl_c)));
 }
 __device__ __forceinline__ double esat_ice(const DevParams &P, double T) {
-    double Tc = T - P.T_0;
-    return P.esi_a * ::exp(P.esi_b * Tc / (Tc + P.esi_c));
+    const double Tc = T - P.T_0;
+    return P.esi_a * exp64(P.esi_b * Tc * (1.0 / (Tc + P.esi_c)));
 }
 __device__ __forceinline__ double q_of_e(const DevParams &P, double e, double p) {
     return P.eps * e / (p - P.one_m_eps * e);
@@ -80,34 +95,31 @@ __device__ __forceinline__ void cleanup(const DevParams &P, Pt &w, Pt &d, double
     }
 }
 
-__device__ __forceinline__ void adjust(const DevParams &P, Pt &w, Pt &d, double p, double rho) {
+__device__ __forceinline__ void adjust(const DevParams &P, bool warm, Pt &w, Pt &d, double p, double rho) {
     cleanup(P, w, d, w.qc, d.qc, w.nc, d.nc, P.L_v);
     cleanup(P, w, d, w.qr, d.qr, w.nr, d.nr, P.L_v);
-    if (P.warm) return;
+    if (warm) return;
     cleanup(P, w, d, w.qi, d.qi, w.ni, d.ni, P.L_s);
     cleanup(P, w, d, w.qs, d.qs, w.ns, d.ns, P.L_s);
     cleanup(P, w, d, w.qg, d.qg, w.ng, d.ng, P.L_s);
-    // homogeneous freezing of all cloud
-    if (w.T < P.T_hom && w.qc > 0.0) {
+    if (w.T < P.T_hom && w.qc > 0.0) {           // homogeneous freezing of all cloud
         double m = w.qc, nn = w.nc;
         d.qc -= m; w.qc = 0.0; d.nc -= nn; w.nc = 0.0;
         w.qi += m; d.qi += m; w.ni += nn; d.ni += nn;
         double h = P.L_f * m * P.inv_cp;
         w.T += h; d.T += h;
     }
-    // melting of all ice
-    if (w.T > P.T_0 && w.qi > 0.0) {
+    if (w.T > P.T_0 && w.qi > 0.0) {             // melting of all ice
         double m = w.qi, nn = w.ni;
         d.qi -= m; w.qi = 0.0; d.ni -= nn; w.ni = 0.0;
         w.qc += m; d.qc += m; w.nc += nn; d.nc += nn;
         double h = -P.L_f * m * P.inv_cp;
         w.T += h; d.T += h;
     }
-    // Cooper (1986) nucleation where ice-supersaturated
-    if (w.T < P.T_nuc) {
+    if (w.T < P.T_nuc) {                          // Cooper (1986) nucleation
         double qsi = q_of_e(P, esat_ice(P, w.T), p);
         if (w.qv > qsi) {
-            double nin = ::fmin(P.cooper_a * ::exp(P.cooper_b * (P.T_0 - w.T)), P.cooper_max) / rho;
+            double nin = ::fmin(P.cooper_a * exp64(P.cooper_b * (P.T_0 - w.T)), P.cooper_max) / rho;
             if (nin > w.ni) {
                 double dn = nin - w.ni;
                 double dq = ::fmin(dn * P.m_i0, w.qv - qsi);
@@ -123,44 +135,47 @@ __device__ __forceinline__ void adjust(const DevParams &P, Pt &w, Pt &d, double 
 
 // ---- saturation adjustment (binary64 in every mode) -----------------------
 // Fixed-count Newton on cp*delta - Lv*(qv - qs(T+delta)) = 0 from delta = 0.
-__device__ __forceinline__ bool satadj(const DevParams &P, Pt &w, Pt &d, double p) {
-    double qsl = q_of_e(P, esat_liq(P, w.T), p);
-    if (!(w.qv > qsl || w.qc > 0.0)) return false;
-    double delta = 0.0;
-    for (int it = 0; it < P.newton_iters; ++it) {
-        double Tc = (w.T + delta) - P.T_0;
-        double rtc = 1.0 / (Tc + P.esl_c);
-        double es = P.esl_a * ::exp(P.esl_b * Tc * rtc);
-        double rden = 1.0 / (p - P.one_m_eps * es);
-        double qs = P.eps * es * rden;
-        double f = P.cp * delta - P.L_v * (w.qv - qs);
-        double fp = P.cp + P.L_v * qs * (p * rden) * P.esl_bc * (rtc * rtc);
+// es_in is the liquid saturation pressure at T_in (already known from the
+// activity test); on return es_out holds it at the final temperature.
+__device__ __forceinline__ bool satadj(const DevParams &P, int iters, Pt &w, Pt &d, double p,
+                                       double T_in, double es_in, double &es_out) {
+    double es0 = (w.T == T_in) ? es_in : esat_liq(P, w.T);
+    es_out = es0;
+    if (!(w.qv > q_of_e(P, es0, p) || w.qc > 0.0)) return false;
+    double delta = 0.0, es = es0;
+    for (int it = 0; it < iters; ++it) {
+        const double Tc = (w.T + delta) - P.T_0;
+        const double rtc = 1.0 / (Tc + P.esl_c);
+        if (it > 0) es = P.esl_a * exp64(P.esl_b * Tc * rtc);
+        const double rden = 1.0 / (p - P.one_m_eps * es);
+        const double qs = P.eps * es * rden;
+        const double f = P.cp * delta - P.L_v * (w.qv - qs);
+        const double fp = P.cp + P.L_v * qs * (p * rden) * P.esl_bc * (rtc * rtc);
         delta -= f / fp;
     }
-    bool bad;
-    {
-        double qs = q_of_e(P, esat_liq(P, w.T + delta), p);
-        double res = ::fabs(P.cp * delta - P.L_v * (w.qv - qs)) / (P.L_v * qs);
-        bad = !(res <= P.newton_rtol);
-    }
-    double dq = P.cp * delta / P.L_v;
+    const double T1 = w.T + delta;
+    const double es1 = esat_liq(P, T1);
+    const double qs1 = q_of_e(P, es1, p);
+    const bool bad = !(::fabs(P.cp * delta - P.L_v * (w.qv - qs1)) / (P.L_v * qs1) <= P.newton_rtol);
+    const double dq = P.cp * delta / P.L_v;
     if (w.qc + dq >= 0.0) {
-        bool newcloud = (w.qc == 0.0 && dq > 0.0);
+        const bool newcloud = (w.qc == 0.0 && dq > 0.0);
         w.qc += dq; d.qc += dq;
         w.qv -= dq; d.qv -= dq;
         w.T += delta; d.T += delta;
+        es_out = es1;
         if (newcloud) {
-            double target = ::fmax(w.nc, P.n_act);
-            double add = target - w.nc;
+            const double add = ::fmax(w.nc, P.n_act) - w.nc;
             w.nc += add; d.nc += add;
         }
-    } else {
-        double m = w.qc;
+    } else {                                      // all cloud evaporates
+        const double m = w.qc;
         w.qv += m; d.qv += m;
-        double h = -P.L_v * m * P.inv_cp;
+        const double h = -P.L_v * m * P.inv_cp;
         w.T += h; d.T += h;
         d.qc -= m; w.qc = 0.0;
         d.nc -= w.nc; w.nc = 0.0;
+        es_out = esat_liq(P, w.T);
     }
     return bad;
 }
@@ -168,68 +183,93 @@ __device__ __forceinline__ bool satadj(const DevParams &P, Pt &w, Pt &d, double 
 // ---- the 12 process rates ------------------------------------------------
 enum { AUTO, ACCR, REVP, DEPI, DEPS, IAUT, SACI, SACW, GACW, FRZR, SMLT, GMLT };
 
+// esl is the liquid saturation pressure at w.T.  Powers of a slope are built
+// from lambda^-1 by multiplication; only the non-integer powers need exp.
 template <class R>
-__device__ __forceinline__ void rates(const DevParams &P, const Pt &w, double p, double rho,
-                                      double rfac_d, R r[12]) {
+__device__ __forceinline__ void rates(const DevParams &P, bool warm, const Pt &w, double p, double rho,
+                                      double ln_rho, double rfac, double esl, R r[12]) {
     using M = Mth<R>;
 #pragma unroll
     for (int j = 0; j < 12; ++j) r[j] = R(0);
     const double qmin = P.q_min;
     const bool cP = w.qc >= qmin, rP = w.qr >= qmin;
-    const bool iP = !P.warm && w.qi >= qmin, sP = !P.warm && w.qs >= qmin, gP = !P.warm && w.qg >= qmin;
+    const bool iP = !warm && w.qi >= qmin, sP = !warm && w.qs >= qmin, gP = !warm && w.qg >= qmin;
     if (!(cP || rP || iP || sP || gP)) return;
-    const bool cold = !P.warm && w.T < P.T_0, hot = !P.warm && w.T > P.T_0;
-    // saturation pressures and ratios in binary64
-    const double esl = esat_liq(P, w.T), esi = esat_ice(P, w.T);
+    const bool cold = !warm && w.T < P.T_0, hot = !warm && w.T > P.T_0;
+    const bool revp = rP && w.qc == 0.0;
+    const bool dep = cold && (iP || sP);
+    // saturation ratios in binary64
     const double Sl_m1 = w.qv / q_of_e(P, esl, p) - 1.0;
-    const double Si_m1 = w.qv / q_of_e(P, esi, p) - 1.0;
+    double esi = 0.0, Si_m1 = 0.0;
+    if (dep) {
+        esi = esat_ice(P, w.T);
+        Si_m1 = w.qv / q_of_e(P, esi, p) - 1.0;
+    }
 
-    const R T = R(w.T), rh = R(rho), rf = R(rfac_d);
+    const R T = R(w.T), rh = R(rho), lrh = R(ln_rho), rf = R(rfac);
     const R dT0 = T - R(P.T_0);
-    const R Dv = R(P.Dv0) * M::pow(T / R(P.T_0), R(P.Dv_exp)) * (R(1e5) / R(p));
-    const R KRT2 = R(P.K_a) * R(P.R_v) * T * T;
-    const R twopi = R(6.283185307179586);
-    const R qc = R(w.qc), qr = R(w.qr), qi = R(w.qi), qs = R(w.qs), qg = R(w.qg);
-
-    R lr = R(0), li = R(0), ls = R(0), lg = R(0);
-    if (rP) lr = clampv(M::cbrt(R(P.lam_coef[0]) * R(w.nr) / qr), R(P.lam_lo[0]), R(P.lam_hi[0]));
-    if (iP) li = clampv(M::cbrt(R(P.lam_coef[1]) * R(w.ni) / qi), R(P.lam_lo[1]), R(P.lam_hi[1]));
-    if (sP) ls = clampv(M::sqrt(M::sqrt(R(P.lam_coef[2]) / (rh * qs))), R(P.lam_lo[2]), R(P.lam_hi[2]));
-    if (gP) lg = clampv(M::sqrt(M::sqrt(R(P.lam_coef[3]) / (rh * qg))), R(P.lam_lo[3]), R(P.lam_hi[3]));
+    // ln lambda, clamped to the mean-diameter bounds, and lambda^-1
+    R lnqc = R(0), lnqr = R(0), llr = R(0), llg = R(0), lls = R(0);
+    R ilr = R(0), ili = R(0), ils = R(0), ilg = R(0);
+    if (cP) lnqc = M::log(R(w.qc));
+    if (rP) {
+        lnqr = M::log(R(w.qr));
+        llr = clampv((R(P.ln_lam_coef[0]) + M::log(R(w.nr)) - lnqr) * R(1.0 / 3.0),
+                     R(P.ln_lam_lo[0]), R(P.ln_lam_hi[0]));
+        ilr = M::exp(-llr);
+    }
+    if (iP && cold) {
+        const R lli = clampv((R(P.ln_lam_coef[1]) + M::log(R(w.ni) / R(w.qi))) * R(1.0 / 3.0),
+                             R(P.ln_lam_lo[1]), R(P.ln_lam_hi[1]));
+        ili = M::exp(-lli);
+    }
+    if (sP && (cold || hot)) {
+        lls = clampv((R(P.ln_lam_coef[2]) - lrh - M::log(R(w.qs))) * R(0.25), R(P.ln_lam_lo[2]), R(P.ln_lam_hi[2]));
+        ils = M::exp(-lls);
+    }
+    if (gP && (cold || hot)) {
+        llg = clampv((R(P.ln_lam_coef[3]) - lrh - M::log(R(w.qg))) * R(0.25), R(P.ln_lam_lo[3]), R(P.ln_lam_hi[3]));
+        ilg = M::exp(-llg);
+    }
 
     if (cP && w.nc > 0.0) {
-        const R Nc = R(w.nc) * rh * R(1e-6);
-        r[AUTO] = R(P.auto_a) * M::pow(qc, R(P.auto_qc_exp)) * M::pow(Nc, R(P.auto_nc_exp));
+        const R lnNc = M::log(R(w.nc)) + lrh + R(P.ln_1e6);
+        r[AUTO] = R(P.auto_a) * M::exp(R(P.auto_qc_exp) * lnqc + R(P.auto_nc_exp) * lnNc);
     }
-    if (cP && rP) r[ACCR] = R(P.accr_a) * M::pow(qc * qr, R(P.accr_exp));
-    if (rP && w.qc == 0.0 && Sl_m1 < 0.0) {
-        const R Gl = R(1) / (R(P.L_v) * R(P.L_v) / KRT2 + R(P.R_v) * T / (Dv * R(esl)));
-        r[REVP] = twopi * Gl * R(-Sl_m1) * R(w.nr) / lr;
-    }
-    if (cold && (iP || sP)) {
-        const R Gi = R(1) / (R(P.L_s) * R(P.L_s) / KRT2 + R(P.R_v) * T / (Dv * R(esi)));
-        if (iP) r[DEPI] = twopi * Gi * R(Si_m1) * R(w.ni) / li;
-        if (sP) r[DEPS] = twopi * Gi * R(Si_m1) * R(P.N0_s) / (rh * ls * ls);
+    if (cP && rP) r[ACCR] = R(P.accr_a) * M::exp(R(P.accr_exp) * (lnqc + lnqr));
+    const bool do_revp = revp && Sl_m1 < 0.0;
+    if (do_revp || dep) {
+        const R KRT2 = R(P.K_a) * R(P.R_v) * T * T;
+        const R Dv = R(P.Dv0) * M::exp(R(P.Dv_exp) * M::log(T * R(1.0 / P.T_0))) * (R(1e5) / R(p));
+        if (do_revp) {
+            const R Gl = R(1) / (R(P.L_v) * R(P.L_v) / KRT2 + R(P.R_v) * T / (Dv * R(esl)));
+            r[REVP] = R(P.two_pi) * Gl * R(-Sl_m1) * R(w.nr) * ilr;
+        }
+        if (dep) {
+            const R Gi = R(1) / (R(P.L_s) * R(P.L_s) / KRT2 + R(P.R_v) * T / (Dv * R(esi)));
+            if (iP) r[DEPI] = R(P.two_pi) * Gi * R(Si_m1) * R(w.ni) * ili;
+            if (sP) r[DEPS] = R(P.two_pi) * Gi * R(Si_m1) * R(P.N0_s) / rh * (ils * ils);
+        }
     }
     if (cold) {
         const R eice = M::exp(R(P.ice_t_exp) * dT0);
-        if (iP && w.qi > P.q_i0) r[IAUT] = R(P.iaut_a) * eice * (qi - R(P.q_i0));
-        if (sP) {
-            const R coll = R(P.coll_s) * M::pow(ls, -(R(3) + R(P.fall_b[2]))) * rf;
-            if (iP) r[SACI] = eice * qi * coll;
-            if (cP) r[SACW] = qc * coll;
+        if (iP && w.qi > P.q_i0) r[IAUT] = R(P.iaut_a) * eice * (R(w.qi) - R(P.q_i0));
+        if (sP && (iP || cP)) {
+            // lambda_s^-(3+b) = lambda_s^-3 * exp(-b ln lambda_s)
+            const R coll = R(P.coll_s) * (ils * ils * ils) * M::exp(R(P.coll_exp_s + 3.0) * lls) * rf;
+            if (iP) r[SACI] = eice * R(w.qi) * coll;
+            if (cP) r[SACW] = R(w.qc) * coll;
         }
-        if (gP && cP) r[GACW] = R(P.coll_g) * M::pow(lg, -(R(3) + R(P.fall_b[3]))) * rf * qc;
+        if (gP && cP) r[GACW] = R(P.coll_g) * (ilg * ilg * ilg) * M::exp(R(P.coll_exp_g + 3.0) * llg) * rf * R(w.qc);
         if (rP) {
-            const R n0r = rh * R(w.nr) * lr;
-            const R l2 = lr * lr, l7 = l2 * l2 * l2 * lr;
-            r[FRZR] = R(P.frzr_coef) * n0r / rh * (M::exp(R(P.bigg_a) * (R(P.T_0) - T)) - R(1)) / l7;
+            const R il2 = ilr * ilr, il6 = il2 * il2 * il2;
+            r[FRZR] = R(P.frzr_coef) * R(w.nr) * (M::exp(R(P.bigg_a) * (R(P.T_0) - T)) - R(1)) * il6;
         }
     }
-    if (hot) {
-        const R melt = twopi * R(P.K_a) * dT0 / (rh * R(P.L_f));
-        if (sP) r[SMLT] = melt * R(P.N0_s) / (ls * ls);
-        if (gP) r[GMLT] = melt * R(P.N0_g) / (lg * lg);
+    if (hot && (sP || gP)) {
+        const R melt = R(P.two_pi) * R(P.K_a) * dT0 / (rh * R(P.L_f));
+        if (sP) r[SMLT] = melt * R(P.N0_s) * (ils * ils);
+        if (gP) r[GMLT] = melt * R(P.N0_g) * (ilg * ilg);
     }
 }
 
@@ -280,8 +320,7 @@ __device__ __forceinline__ void apply_rates(const DevParams &P, Pt &w, Pt &d, co
     if (lim) { d.q -= w.q; w.q = 0.0; d.n -= w.n; w.n = 0.0; }        \
     else { w.q -= sq; d.q -= sq; w.n -= ns_; d.n -= ns_; }            \
     w.q += gq; d.q += gq; w.n += gn; d.n += gn;
-    // vapour has no number
-    if (lv) { d.qv -= w.qv; w.qv = 0.0; } else { w.qv -= sq_v; d.qv -= sq_v; }
+    if (lv) { d.qv -= w.qv; w.qv = 0.0; } else { w.qv -= sq_v; d.qv -= sq_v; }   // vapour: no number
     w.qv += g_v; d.qv += g_v;
     CASIM_APPLY(qc, nc, lc, sq_c, 0.0, sq_c * mm_c, 0.0)
     CASIM_APPLY(qr, nr, lr, sq_r, g_r, sq_r * mm_r, ng_r)
@@ -292,135 +331,163 @@ __device__ __forceinline__ void apply_rates(const DevParams &P, Pt &w, Pt &d, co
     w.T += dTh; d.T += dTh;
 }
 
-// Fall speeds of category c (0..3 = r, i, s, g) for mass and number.
-template <class R>
-__device__ __forceinline__ void fall(const DevParams &P, int c, double q, double n, double rho,
-                                     double rfac, double &vq, double &vn) {
+// ---- sedimentation of one category over one chunk --------------------------
+// Mass- and number-weighted fall speeds a Gamma(4+b)/6 lambda^-b and
+// a Gamma(1+b) lambda^-b, times (rho_0/rho)^1/2, capped at v_max.
+template <class R, int C>
+__device__ __forceinline__ void sediment(const DevParams &P, int cat, int ns, double dts, double *lds,
+                                         int g, int c, bool need, double rho, double ln_rho, double rfac,
+                                         double inv_rdz, bool surf, double &q, double &n, double &dq,
+                                         double &dn, double &psq, double &psn, bool &out_nz) {
     using M = Mth<R>;
-    R lam;
-    if (c < 2) lam = M::cbrt(R(P.lam_coef[c]) * R(n) / R(q));
-    else       lam = M::sqrt(M::sqrt(R(P.lam_coef[c]) / (R(rho) * R(q))));
-    lam = clampv(lam, R(P.lam_lo[c]), R(P.lam_hi[c]));
-    const R lb = M::pow(lam, R(P.fall_b[c]));
-    vq = double(M::fmin(R(P.vq_coef[c]) / lb * R(rfac), R(P.v_max[c])));
-    vn = double(M::fmin(R(P.vn_coef[c]) / lb * R(rfac), R(P.v_max[c])));
-}
-
-// All substeps of one sedimenting category at one level.  carry holds, per
-// (moment, substep), the flux that left the level above during that substep;
-// on return it holds the fluxes leaving this level.
-template <class R>
-__device__ __forceinline__ void sediment(const DevParams &P, const SweepArgs &a, int c, double *carry,
-                                         double rho, double rfac, double inv_rdz, bool surf,
-                                         double &q, double &n, double &dq, double &dn,
-                                         double &psq, double &psn, bool &out_nz) {
-    const int ns = a.nsub[c];
-    const double dts = a.dt / ns;
-    double *cq = carry + (size_t)a.slot0[c] * kWave;
-    double *cn = cq + (size_t)ns * kWave;
+    constexpr int L = kWave / C;
+    double *cq = lds;                 // [s][c] flux of mass leaving the previous chunk
+    double *cn = lds + ns * C;        // [s][c] flux of number
+    const R ln_coef = R(P.ln_lam_coef[cat]), lo = R(P.ln_lam_lo[cat]), hi = R(P.ln_lam_hi[cat]);
+    const R mb = R(-P.fall_b[cat]), vqc = R(P.vq_coef[cat]), vnc = R(P.vn_coef[cat]), vmax = R(P.v_max[cat]);
     for (int s = 0; s < ns; ++s) {
         double Fq = 0.0, Fn = 0.0;
-        if (q >= P.q_min) {
-            double vq, vn;
-            fall<R>(P, c, q, n, rho, rfac, vq, vn);
+        if (need && q >= P.q_min) {
+            R ll;
+            if (cat < 2) ll = (ln_coef + M::log(R(n) / R(q))) * R(1.0 / 3.0);
+            else         ll = (ln_coef - R(ln_rho) - M::log(R(q))) * R(0.25);
+            ll = clampv(ll, lo, hi);
+            const R e = M::exp(mb * ll) * R(rfac);
+            const double vq = double(M::fmin(vqc * e, vmax));
+            const double vn = double(M::fmin(vnc * e, vmax));
             Fq = rho * q * vq;
             Fn = rho * n * vn;
         }
-        const double iq = dts * (cq[s * kWave] - Fq) * inv_rdz;
-        const double in_ = dts * (cn[s * kWave] - Fn) * inv_rdz;
-        q += iq; dq += iq; n += in_; dn += in_;
-        cq[s * kWave] = Fq; cn[s * kWave] = Fn;
+        double in_q, in_n;
+        if constexpr (L == 1) {
+            in_q = cq[s * C + c];
+            in_n = cn[s * C + c];
+        } else {
+            const double up_q = __shfl_up(Fq, C), up_n = __shfl_up(Fn, C);
+            const double cr_q = cq[s * C + c], cr_n = cn[s * C + c];
+            in_q = g == 0 ? cr_q : up_q;
+            in_n = g == 0 ? cr_n : up_n;
+        }
+        if (need) {
+            const double iq = dts * (in_q - Fq) * inv_rdz;
+            const double in_ = dts * (in_n - Fn) * inv_rdz;
+            q += iq; dq += iq; n += in_; dn += in_;
+        }
+        if (g == L - 1) { cq[s * C + c] = Fq; cn[s * C + c] = Fn; }
         out_nz |= (Fq != 0.0) | (Fn != 0.0);
         if (surf) { psq += Fq * dts; psn += Fn * dts; }
     }
 }
 
-template <bool MIX>
-__global__ __launch_bounds__(256) void sweep_kernel(DevParams P, SweepArgs a) {
+template <bool MIX, bool FAST, int C>
+__global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) {
     using R = typename std::conditional<MIX, float, double>::type;
-    extern __shared__ double carry_lds[];
+    constexpr int L = kWave / C;
+    const DevParams &P = params<FAST>(Prt);
+    extern __shared__ double lds_all[];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    double *carry = carry_lds + (size_t)wave * a.nslots * kWave + lane;   // slot j at carry[j*64]
-    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = col < a.ncol;
-    const double dt = a.dt;
-    const double inv_dt = 1.0 / dt;
-    const int ncat = P.warm ? 1 : 4;
-    const bool do_adj = P.stages & CASIM_STAGE_ADJUST, do_sat = P.stages & CASIM_STAGE_SATADJ;
-    const bool do_rates = P.stages & CASIM_STAGE_RATES, do_sed = P.stages & CASIM_STAGE_SED;
+    const int wib = threadIdx.x / kWave;
+    const int g = lane / C, c = lane % C;
+    double *lds = lds_all + (size_t)wib * a.nslots * C;
+    const int64_t col = ((int64_t)blockIdx.x * (blockDim.x / kWave) + wib) * C + c;
+    const bool colvalid = col < a.ncol;
+    const double dt = a.dt, inv_dt = 1.0 / dt;
+    const bool warm = a.warm != 0;
+    const int ncat = warm ? 1 : 4;
+    const bool do_adj = a.stages & CASIM_STAGE_ADJUST, do_sat = a.stages & CASIM_STAGE_SATADJ;
+    const bool do_rates = a.stages & CASIM_STAGE_RATES, do_sed = a.stages & CASIM_STAGE_SED;
+    double dts[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dts[j] = dt / a.nsub[j];
 
-    for (int j = 0; j < a.nslots; ++j) carry[j * kWave] = 0.0;
-    bool inflow = false;            // a flux from the level above is non-zero
+    for (int j = lane; j < a.nslots * C; j += kWave) lds[j] = 0.0;
+    unsigned long long carry_cols = 0;   // bit c: a flux enters column c's next chunk from above
+    const unsigned long long cmask = (C == 64) ? ~0ull : ((1ull << C) - 1ull);
     double psurf[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) psurf[j] = 0.0;
+    // the lane holding level 0 of its column accumulates and writes the surface sums
+    const bool surf_lane = colvalid && g == (a.nlev - 1) % L;
     unsigned newton_bad = 0, nonfinite = 0;
 
-    for (int k = a.nlev - 1; k >= 0; --k) {
-        const int64_t ix = (int64_t)k * a.ld + col;
+    for (int k0 = a.nlev - 1; k0 >= 0; k0 -= L) {
+        const int k = k0 - g;
+        const bool vp = colvalid && k >= 0;
+        const int64_t ix = (int64_t)(k < 0 ? 0 : k) * a.ld + col;
         Pt w{}, d{};
-        double p = 1.0, rho = 1.0;
+        double p = 1.0, rho = 1.0, es_l = 1.0;
         bool act = false;
-        if (valid) {
+        if (vp) {
             w.T = a.in[0][ix]; p = a.in[1][ix]; w.qv = a.in[3][ix];
             w.qc = a.in[4][ix]; w.qr = a.in[6][ix]; w.qi = a.in[8][ix];
             w.qs = a.in[10][ix]; w.qg = a.in[12][ix];
-            const bool cond = (w.qc > 0.0) | (w.qr > 0.0) | (!P.warm & ((w.qi > 0.0) | (w.qs > 0.0) | (w.qg > 0.0)));
-            act = cond;
-            if (!cond && (do_adj || do_sat)) {
-                // a condensate-free point changes only if supersaturated
-                if (do_sat) act = w.qv > q_of_e(P, esat_liq(P, w.T), p);
-                if (!act && do_adj && !P.warm && w.T < P.T_nuc)
-                    act = w.qv > q_of_e(P, esat_ice(P, w.T), p);
-            }
+            act = (w.qc > 0.0) | (w.qr > 0.0) | (!warm & ((w.qi > 0.0) | (w.qs > 0.0) | (w.qg > 0.0)));
+            es_l = esat_liq(P, w.T);
+            // a condensate-free point changes only if supersaturated
+            if (!act && do_sat) act = w.qv > q_of_e(P, es_l, p);
+            if (!act && do_adj && !warm && w.T < P.T_nuc) act = w.qv > q_of_e(P, esat_ice(P, w.T), p);
         }
-        const unsigned long long bal = __ballot((int)(act || inflow));
-        if (bal == 0ull) {
-            if (valid) {
+        const double T_in = w.T;
+        const unsigned long long bal = __ballot((int)act);
+        if (bal == 0ull && carry_cols == 0ull) {
+            if (vp) {
 #pragma unroll
                 for (int f = 0; f < CASIM_NTEND; ++f) a.tend[f][ix] = 0.0;
             }
             continue;
         }
-        if (act || inflow) {
+        unsigned long long colbits = carry_cols;
+#pragma unroll
+        for (int gg = 0; gg < L; ++gg) colbits |= (bal >> (gg * C)) & cmask;
+        const bool need = vp && (act || ((colbits >> c) & 1ull));
+        double ln_rho = 0.0;
+        if (need) {
             rho = a.in[2][ix];
             w.nc = a.in[5][ix]; w.nr = a.in[7][ix]; w.ni = a.in[9][ix];
             w.ns = a.in[11][ix]; w.ng = a.in[13][ix];
+            ln_rho = log64(rho);
         }
         const double rfac = ::sqrt(P.rho_0 / rho);
         if (act) {
-            if (do_adj) adjust(P, w, d, p, rho);
-            if (do_sat) newton_bad += satadj(P, w, d, p) ? 1u : 0u;
+            if (do_adj) adjust(P, warm, w, d, p, rho);
+            double es_now = es_l;
+            if (do_sat) newton_bad += satadj(P, a.newton_iters, w, d, p, T_in, es_l, es_now) ? 1u : 0u;
             if (do_rates) {
+                // without the adjustment stage the clean-up may still have moved T
+                if (!do_sat && w.T != T_in) es_now = esat_liq(P, w.T);
                 R r[12];
-                rates<R>(P, w, p, rho, rfac, r);
+                rates<R>(P, warm, w, p, rho, ln_rho, rfac, es_now, r);
                 apply_rates<R>(P, w, d, r, dt);
             }
         }
         bool out_nz = false;
-        if ((act || inflow) && do_sed) {
-            const double inv_rdz = 1.0 / (rho * a.dz[k]);
-            const bool surf = (k == 0);
-            sediment<R>(P, a, 0, carry, rho, rfac, inv_rdz, surf, w.qr, w.nr, d.qr, d.nr, psurf[0], psurf[4], out_nz);
+        if (do_sed) {
+            double inv_rdz = 0.0;
+            if (need) inv_rdz = 1.0 / (rho * a.dz[k < 0 ? 0 : k]);
+            const bool surf = vp && k == 0;
+            sediment<R, C>(P, 0, a.nsub[0], dts[0], lds + a.slot0[0] * C, g, c, need, rho, ln_rho, rfac,
+                           inv_rdz, surf, w.qr, w.nr, d.qr, d.nr, psurf[0], psurf[4], out_nz);
             if (ncat > 1) {
-                sediment<R>(P, a, 1, carry, rho, rfac, inv_rdz, surf, w.qi, w.ni, d.qi, d.ni, psurf[1], psurf[5], out_nz);
-                sediment<R>(P, a, 2, carry, rho, rfac, inv_rdz, surf, w.qs, w.ns, d.qs, d.ns, psurf[2], psurf[6], out_nz);
-                sediment<R>(P, a, 3, carry, rho, rfac, inv_rdz, surf, w.qg, w.ng, d.qg, d.ng, psurf[3], psurf[7], out_nz);
+                sediment<R, C>(P, 1, a.nsub[1], dts[1], lds + a.slot0[1] * C, g, c, need, rho, ln_rho, rfac,
+                               inv_rdz, surf, w.qi, w.ni, d.qi, d.ni, psurf[1], psurf[5], out_nz);
+                sediment<R, C>(P, 2, a.nsub[2], dts[2], lds + a.slot0[2] * C, g, c, need, rho, ln_rho, rfac,
+                               inv_rdz, surf, w.qs, w.ns, d.qs, d.ns, psurf[2], psurf[6], out_nz);
+                sediment<R, C>(P, 3, a.nsub[3], dts[3], lds + a.slot0[3] * C, g, c, need, rho, ln_rho, rfac,
+                               inv_rdz, surf, w.qg, w.ng, d.qg, d.ng, psurf[3], psurf[7], out_nz);
             }
         }
-        inflow = out_nz;
-        if (valid) {
-            double o[12] = {d.T * inv_dt, d.qv * inv_dt, d.qc * inv_dt, d.nc * inv_dt,
-                            d.qr * inv_dt, d.nr * inv_dt, d.qi * inv_dt, d.ni * inv_dt,
-                            d.qs * inv_dt, d.ns * inv_dt, d.qg * inv_dt, d.ng * inv_dt};
+        carry_cols = (__ballot((int)(g == L - 1 && out_nz)) >> ((L - 1) * C)) & cmask;
+        if (vp) {
+            const double o[12] = {d.T * inv_dt, d.qv * inv_dt, d.qc * inv_dt, d.nc * inv_dt,
+                                  d.qr * inv_dt, d.nr * inv_dt, d.qi * inv_dt, d.ni * inv_dt,
+                                  d.qs * inv_dt, d.ns * inv_dt, d.qg * inv_dt, d.ng * inv_dt};
             double sum = 0.0;
 #pragma unroll
             for (int f = 0; f < CASIM_NTEND; ++f) { a.tend[f][ix] = o[f]; sum += ::fabs(o[f]); }
             nonfinite += ::isfinite(sum) ? 0u : 1u;
         }
     }
-    if (valid) {
+    if (surf_lane) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) a.sfc[j][col] = psurf[j];
     }
@@ -429,9 +496,9 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams P, SweepArgs a) {
 }
 
 // X += dt * tend for the 12 prognostic fields; q and n clipped at 0.
-__global__ __launch_bounds__(256) void apply_kernel(SweepArgs a, double dt, int64_t npts_ld) {
+__global__ __launch_bounds__(256) void apply_kernel(SweepArgs a, double dt, int64_t npts) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npts_ld) return;
+    if (i >= npts) return;
     const int64_t k = i / a.ncol, c = i - k * a.ncol;
     const int64_t ix = k * a.ld + c;
     double *T = const_cast<double *>(a.in[0]);
@@ -444,23 +511,64 @@ __global__ __launch_bounds__(256) void apply_kernel(SweepArgs a, double dt, int6
     }
 }
 
-hipError_t launch_sweep(const DevParams &P, const SweepArgs &a, hipStream_t stream) {
-    static int wpb = 0;
-    if (wpb == 0) {
-        const char *e = getenv("CASIM_WAVES_PER_BLOCK");
-        wpb = e ? atoi(e) : 1;
-        if (wpb < 1 || wpb > 4) wpb = 1;
+namespace {
+
+int env_int(const char *name, int dflt) {
+    const char *e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
+template <bool MIX, bool FAST>
+hipError_t launch_c(int C, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &P,
+                    const SweepArgs &a) {
+    switch (C) {
+        case 16: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 16>), grid, block, lds, s, P, a); break;
+        case 32: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 32>), grid, block, lds, s, P, a); break;
+        default: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 64>), grid, block, lds, s, P, a); break;
     }
-    int w = wpb;
-    size_t lds = (size_t)w * a.nslots * kWave * sizeof(double);
-    while (w > 1 && lds > 65536) { --w; lds = (size_t)w * a.nslots * kWave * sizeof(double); }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Columns per wavefront: enough wavefronts to give every SIMD of the chip
+// (256 CUs x 4) several to interleave, without giving up full 128-byte rows.
+static int pick_columns_per_wave(int64_t ncol) {
+    const int forced = env_int("CASIM_COLS_PER_WAVE", 0);
+    if (forced == 16 || forced == 32 || forced == 64) return forced;
+    const int64_t target_waves = 4096;
+    if (ncol / 64 >= target_waves) return 64;
+    if (ncol / 32 >= target_waves) return 32;
+    return 16;
+}
+
+hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream) {
+    const int C = pick_columns_per_wave(a.ncol);
+    int wpb = env_int("CASIM_WAVES_PER_BLOCK", 1);
+    if (wpb < 1 || wpb > 4) wpb = 1;
+    size_t lds = (size_t)wpb * a.nslots * C * sizeof(double);
+    while (wpb > 1 && lds > 65536) { --wpb; lds = (size_t)wpb * a.nslots * C * sizeof(double); }
     if (lds > 65536) return hipErrorInvalidValue;
-    const int threads = w * kWave;
-    const int64_t blocks = (a.ncol + threads - 1) / threads;
-    if (P.mode == CASIM_MODE_FP32MIX)
-        hipLaunchKernelGGL(sweep_kernel<true>, dim3((unsigned)blocks), dim3(threads), lds, stream, P, a);
-    else
-        hipLaunchKernelGGL(sweep_kernel<false>, dim3((unsigned)blocks), dim3(threads), lds, stream, P, a);
+    const int64_t waves = (a.ncol + C - 1) / C;
+    const int64_t blocks = (waves + wpb - 1) / wpb;
+    const dim3 grid((unsigned)blocks), block(wpb * kWave);
+    const bool mix = a.mode == CASIM_MODE_FP32MIX;
+    if (mix) return fast ? launch_c<true, true>(C, grid, block, lds, stream, P, a)
+                         : launch_c<true, false>(C, grid, block, lds, stream, P, a);
+    return fast ? launch_c<false, true>(C, grid, block, lds, stream, P, a)
+                : launch_c<false, false>(C, grid, block, lds, stream, P, a);
+}
+
+__global__ __launch_bounds__(256) void math_kernel(const double *x, int64_t n, double *e, double *l) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (e) e[i] = exp64(x[i]);
+    if (l) l[i] = log64(x[i]);
+}
+
+hipError_t launch_math(const double *x, int64_t n, double *e, double *l, hipStream_t stream) {
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(math_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, n, e, l);
     return hipGetLastError();
 }
 

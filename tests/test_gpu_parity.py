@@ -17,6 +17,9 @@ TOL = 1e-12
 
 def _assert_parity(oracle_lib, st, dz, dt, tol=TOL, tag="", **kw):
     okw = {k: v for k, v in kw.items() if k in ("stages", "warm", "newton_iters")}
+    if "constants" in kw:
+        okw["warm"] = bool(kw["constants"].warm)
+        okw["stages"] = kw["constants"].stages
     tg, sg, status, _ = run_gpu(st, dz, dt, **kw)
     ncol = kw.get("ncol") or st.shape[2]
     to, so, fails = oracle_lib.step(st[:, :, :ncol], dz, dt, return_fails=True, **okw)
@@ -161,3 +164,34 @@ def test_argument_errors_on_device():
     st = casim.make_state(dev, dz, tend, sfc, ld=4)      # ld < ncol
     assert casim.lib().casim_step(st, 8, 3, 2.0, None) == -1
     assert casim.lib().casim_step(st, 2, 600, 2.0, None) == -1
+
+
+@pytest.mark.parametrize("cols_per_wave", [16, 32, 64])
+@pytest.mark.parametrize("generic", [False, True])
+def test_tile_widths_and_runtime_constants(oracle_lib, cols_per_wave, generic, monkeypatch):
+    """Every wavefront tile (C columns x 64/C levels) and both the compiled-in
+    and the run-time constant kernels, on a ragged domain with a partial last
+    chunk (nlev not a multiple of 64/C) and several substeps."""
+    from paper_2010_14823_amd import casim
+    monkeypatch.setenv("CASIM_COLS_PER_WAVE", str(cols_per_wave))
+    cfg = synth.Config("tiles", 13, 7, 101, 17, 0.5, deep=True)
+    f, dz, _ = synth.generate(cfg)
+    st = synth.stack(f)
+    c = casim.default_constants(flags=casim.FLAG_GENERIC if generic else 0)
+    for dt in (2.0, 7.0):
+        _assert_parity(oracle_lib, st, dz, dt, constants=c,
+                       tag="C%d generic=%d dt=%g" % (cols_per_wave, generic, dt))
+
+
+@pytest.mark.parametrize("cols_per_wave", [16, 64])
+def test_fp32mix_tiles_agree(oracle_lib, cols_per_wave, monkeypatch):
+    """The mixed-precision path gives the same answer at every tile width (to
+    binary32 rounding) and stays close to the binary64 oracle."""
+    from paper_2010_14823_amd import casim
+    monkeypatch.setenv("CASIM_COLS_PER_WAVE", str(cols_per_wave))
+    cfg, st, dz, _ = config_state("c0")
+    tg, sg, status, _ = run_gpu(st, dz, cfg.dt, mode=casim.MODE_FP32MIX)
+    to, so = oracle_lib.step(st, dz, cfg.dt)
+    errs = field_errors(tg, sg, to, so)
+    print("fp32mix C=%d" % cols_per_wave, {k: float("%.3g" % v) for k, v in errs.items()})
+    assert max(errs.values()) < 1e-3, errs
