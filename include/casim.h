@@ -187,6 +187,110 @@ const char *casim_strerror(int code);
  * uses for this grid and dt: max(1, ceil(v_max dt / min dz)).  Host only. */
 int casim_nsub(const double *dz_host, int32_t nlev, double dt, int32_t nsub_out[4]);
 
+/* ======================================================================
+ * Learned surrogate of the process-rate block.
+ *
+ * A multilayer perceptron maps a grid point's state after saturation
+ * adjustment to its 12 process rates (AUTO ACCR REVP DEPI DEPS IAUT SACI SACW
+ * GACW FRZR SMLT GMLT).  Features (float32, 12 per point): ln T, ln p,
+ * ln rho, ln(q + 1e-12) for qv, qc, then ln(n + 1) for nc, and likewise
+ * (q, n) for rain and ice, then ln(q + 1e-12) for snow and graupel (feature
+ * order T, p, rho, qv, qc, nc, qr, nr, qi, ni, qs, qg).  Targets:
+ * asinh(rate / 1e-12 kg kg-1 s-1).  Gate word (uint16): bit j set when rate
+ * j's condition holds (its categories present and its temperature side);
+ * bit 12 set when the point is supersaturated over ice.  Closed gates are
+ * exact zeros in the plain method and are masked out of training.
+ *
+ * Network: 12 -> 128 -> 128 -> 128 -> 12 with SiLU hidden activations on
+ * standardised features and targets; parameters in one float32 vector of
+ * CASIM_MLP_NPARAMS values, ordered W1 (12x128, row = input), b1, W2
+ * (128x128), b2, W3, b3, W4 (128x12), b4.  Training (float32 forward,
+ * backward and Adam) and inference (bfloat16 weights and activations on the
+ * matrix cores, float32 accumulation) run in the library's kernels.
+ * ==================================================================== */
+#define CASIM_MLP_NIN     12
+#define CASIM_MLP_NHID    128
+#define CASIM_MLP_NOUT    12
+#define CASIM_MLP_NPARAMS 36236
+#define CASIM_MLP_MAX_BATCH 16384
+#define CASIM_GATE_SUPERSAT_ICE (1u << 12)
+
+/* Normalisation and trust-region statistics of a training set. */
+typedef struct casim_mlp_stats {
+    float x_mean[12], x_std[12];   /* features                               */
+    float x_min[12], x_max[12];    /* training range of every feature        */
+    float y_mean[12], y_std[12];   /* scaled targets over open gates         */
+    float cov_inv[144];            /* inverse covariance of standardised features */
+    float maha_q999;               /* 99.9th percentile of the squared Mahalanobis distance */
+    float reserved[3];
+} casim_mlp_stats;
+
+/* Rate samples from the plain binary64 path: every point where anything can
+ * happen is selected with probability keep_prob by a counter-based hash
+ * (splitmix64) of (seed, point index k*ncol + c); the first max_samples
+ * selected points in point order get their features, their 12 plain rates
+ * (float32, kg/kg/s) and their gate word written.  *n_written (host)
+ * receives the number written, *n_selected (host, may be NULL) the number
+ * selected; max_samples = 0 only counts.  Synchronous.  Device buffers feat
+ * and rates hold max_samples x 12 floats, gates max_samples words.  Errors as
+ * casim_step, plus EINVAL for keep_prob outside (0, 1] or max_samples < 0. */
+int casim_rates_dump(const casim_state *s, int64_t ncol, int32_t nlev, double dt, uint64_t seed,
+                     double keep_prob, int64_t max_samples, float *feat, float *rates,
+                     uint16_t *gates, int64_t *n_written, int64_t *n_selected, void *stream);
+
+/* Compute the statistics of n training samples (device arrays as written by
+ * casim_rates_dump), install them and copy them to *out (host).  Synchronous. */
+int casim_mlp_fit_stats(const float *feat, const float *rates, const uint16_t *gates, int64_t n,
+                        casim_mlp_stats *out, void *stream);
+/* Install statistics from the host (e.g. from a checkpoint). */
+int casim_mlp_set_stats(const casim_mlp_stats *st);
+
+/* Standardised network inputs x (n x 12), targets y (n x 12) and loss mask
+ * m (n x 12, 1 where the gate is open) from samples.  Needs statistics. */
+int casim_mlp_prepare(const float *feat, const float *rates, const uint16_t *gates, int64_t n,
+                      float *x, float *y, float *m, void *stream);
+
+/* Initialise parameters (uniform in +-sqrt(6/(fan_in+fan_out)), drawn from a
+ * counter-based hash of (seed, index)) and zero the Adam state. */
+int casim_mlp_init(uint64_t seed);
+/* Copy the float32 parameters to / from host memory (CASIM_MLP_NPARAMS). */
+int casim_mlp_get_params(float *host_params);
+int casim_mlp_set_params(const float *host_params);
+
+/* Loss and gradient of the masked mean squared error over the batch rows
+ * idx[0..batch) of (x, y, m) (idx NULL: rows 0..batch).  grad (device,
+ * CASIM_MLP_NPARAMS) and loss (device, 1 float) are written; the parameters
+ * are not changed.  batch in 1..CASIM_MLP_MAX_BATCH. */
+int casim_mlp_grad(const float *x, const float *y, const float *m, const int32_t *idx, int32_t batch,
+                   float *grad, float *loss, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that gradient; the
+ * batch loss before the update goes to *loss (device, may be NULL). */
+int casim_mlp_train_step(const float *x, const float *y, const float *m, const int32_t *idx,
+                         int32_t batch, float lr, float *loss, void *stream);
+/* float32 forward pass on n standardised inputs -> n x 12 standardised outputs. */
+int casim_mlp_forward(const float *x, int64_t n, float *y, void *stream);
+
+/* Serialise the trained state (format tag, statistics, float32 parameters,
+ * Adam moments and step count) into blob; with blob NULL, *bytes receives the
+ * size needed.  casim_mlp_load restores it (resuming training reproduces the
+ * same parameters). */
+int casim_mlp_save(void *blob, size_t *bytes);
+int casim_mlp_load(const void *blob, size_t bytes);
+
+/* Freeze the current parameters and statistics into the bfloat16 inference
+ * set that CASIM_MODE_SURROGATE steps use.  Errors: ENOSURROGATE (no
+ * parameters or statistics). */
+int casim_surrogate_load(void);
+
+/* Inference on n samples: rates (n x 12, kg/kg/s) from the bfloat16 network
+ * with closed gates zeroed, rates kept non-negative (deposition rates keep
+ * the sign of the ice supersaturation), and fallback[i] = 1 where a feature
+ * lies outside the training range widened by sur_range_margin on each side
+ * or the squared Mahalanobis distance exceeds the threshold (sur_maha_max,
+ * or the training 99.9th percentile when that is 0). */
+int casim_surrogate_infer(const float *feat, const uint16_t *gates, int64_t n, float *rates,
+                          uint8_t *fallback, void *stream);
+
 /* Diagnostics: evaluate the binary64 exponential and logarithm that the
  * step kernels use internally, elementwise on n device values x (x > 0 for a
  * meaningful log), into device arrays exp_out and log_out (either may be

@@ -70,6 +70,8 @@ def lib():
         L.oracle_saturation_adjust.argtypes = [dp, ctypes.c_double, dp, dp, dp, ctypes.c_int32]
         L.oracle_saturation_adjust.restype = ctypes.c_int
         L.oracle_nsub.argtypes = [dp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]
+        L.oracle_point_process.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, dp, dp]
+        L.oracle_point_process.restype = None
         L.oracle_nsub.restype = None
         _lib = L
     return _lib
@@ -137,3 +139,13 @@ def nsub(dz: np.ndarray, dt: float):
     out = (ctypes.c_int32 * 4)()
     lib().oracle_nsub(_dptr(dz), len(dz), float(dt), out)
     return list(out)
+
+
+def point_process(in14, warm=False, newton_iters=5):
+    """(adjusted state (12,), rates (12,)) of one point after clean-up, phase
+    changes and saturation adjustment."""
+    v = np.ascontiguousarray(in14, dtype=np.float64)
+    st = np.zeros(12)
+    r = np.zeros(12)
+    lib().oracle_point_process(_dptr(v), 1 if warm else 0, newton_iters, _dptr(st), _dptr(r))
+    return st, r

@@ -468,6 +468,35 @@ int oracle_saturation_adjust(double *T, double p, double *qv, double *qc, double
     return r;
 }
 
+/* S1-S3 on one point given its 14 input values (T, p, rho, qv, qc, nc, qr,
+ * nr, qi, ni, qs, ns, qg, ng); returns the adjusted state (T, qv, qc, nc, qr,
+ * nr, qi, ni, qs, ns, qg, ng) and the 12 rates S4 evaluates on it. */
+void oracle_point_process(const double in14[14], int32_t warm, int32_t newton_iters,
+                          double state12[12], double rates[12])
+{
+    pstate w; pdelta d;
+    memset(&w, 0, sizeof w); memset(&d, 0, sizeof d);
+    double p = in14[1], rho = in14[2];
+    w.T = in14[0];
+    w.q[V] = in14[3];
+    w.q[C] = in14[4]; w.n[C] = in14[5];
+    w.q[R] = in14[6]; w.n[R] = in14[7];
+    w.q[I] = in14[8]; w.n[I] = in14[9];
+    w.q[S] = in14[10]; w.n[S] = in14[11];
+    w.q[G] = in14[12]; w.n[G] = in14[13];
+    s1_cleanup(&w, &d, warm);
+    if (!warm) s2_phase(&w, &d, p, rho);
+    int bad;
+    s3_satadj(&w, &d, p, newton_iters, &bad);
+    state12[0] = w.T; state12[1] = w.q[V];
+    state12[2] = w.q[C]; state12[3] = w.n[C];
+    state12[4] = w.q[R]; state12[5] = w.n[R];
+    state12[6] = w.q[I]; state12[7] = w.n[I];
+    state12[8] = w.q[S]; state12[9] = w.n[S];
+    state12[10] = w.q[G]; state12[11] = w.n[G];
+    oracle_point_rates(w.T, p, rho, w.q, w.n, warm, rates);
+}
+
 /* column c: S1-S5 at every level (pointwise), then S6 over the column. */
 static int64_t column(const double *const in[14], const double *dz, int64_t col, int64_t ld,
                       int nlev, double dt, double *const tend[12], double *const sfc[8],

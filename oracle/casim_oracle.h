@@ -69,6 +69,12 @@ void oracle_point_rates(double T, double p, double rho, const double q[6],
 int oracle_saturation_adjust(double *T, double p, double *qv, double *qc,
                              double *nc, int32_t newton_iters);
 
+/* Clean-up, phase changes and saturation adjustment of one point (14 input
+ * values in the field order above); returns the adjusted state (T, qv, qc,
+ * nc, qr, nr, qi, ni, qs, ns, qg, ng) and the 12 rates on it. */
+void oracle_point_process(const double in14[14], int32_t warm, int32_t newton_iters,
+                          double state12[12], double rates[12]);
+
 /* Number of sedimentation substeps per category r, i, s, g. */
 void oracle_nsub(const double *dz, int32_t nlev, double dt, int32_t nsub[4]);
 

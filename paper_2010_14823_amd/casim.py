@@ -59,6 +59,20 @@ class StepStatus(ctypes.Structure):
                 ("fallback", ctypes.c_int64), ("inferred", ctypes.c_int64)]
 
 
+_f12 = ctypes.c_float * 12
+MLP_NPARAMS = 36236
+MLP_MAX_BATCH = 16384
+GATE_SUPERSAT_ICE = 1 << 12
+RATE_NAMES = ("AUTO", "ACCR", "REVP", "DEPI", "DEPS", "IAUT", "SACI", "SACW", "GACW", "FRZR", "SMLT", "GMLT")
+FEATURE_NAMES = ("lnT", "lnp", "lnrho", "lnqv", "lnqc", "lnnc", "lnqr", "lnnr", "lnqi", "lnni", "lnqs", "lnqg")
+
+
+class MlpStats(ctypes.Structure):
+    _fields_ = [("x_mean", _f12), ("x_std", _f12), ("x_min", _f12), ("x_max", _f12),
+                ("y_mean", _f12), ("y_std", _f12), ("cov_inv", ctypes.c_float * 144),
+                ("maha_q999", ctypes.c_float), ("reserved", ctypes.c_float * 3)]
+
+
 class CasimError(RuntimeError):
     def __init__(self, code, func):
         self.code = code
@@ -86,6 +100,21 @@ def lib():
             "casim_finalize": [],
             "casim_nsub": [ctypes.POINTER(ctypes.c_double), i32, dbl, ctypes.POINTER(ctypes.c_int32)],
             "casim_debug_math": [vp, i64, vp, vp, vp],
+            "casim_rates_dump": [ctypes.POINTER(State), i64, i32, dbl, ctypes.c_uint64, dbl, i64, vp, vp, vp,
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), vp],
+            "casim_mlp_fit_stats": [vp, vp, vp, i64, ctypes.POINTER(MlpStats), vp],
+            "casim_mlp_set_stats": [ctypes.POINTER(MlpStats)],
+            "casim_mlp_prepare": [vp, vp, vp, i64, vp, vp, vp, vp],
+            "casim_mlp_init": [ctypes.c_uint64],
+            "casim_mlp_get_params": [vp],
+            "casim_mlp_set_params": [vp],
+            "casim_mlp_grad": [vp, vp, vp, vp, i32, vp, vp, vp],
+            "casim_mlp_train_step": [vp, vp, vp, vp, i32, ctypes.c_float, vp, vp],
+            "casim_mlp_forward": [vp, i64, vp, vp],
+            "casim_mlp_save": [vp, ctypes.POINTER(ctypes.c_size_t)],
+            "casim_mlp_load": [vp, ctypes.c_size_t],
+            "casim_surrogate_load": [],
+            "casim_surrogate_infer": [vp, vp, i64, vp, vp, vp],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -225,3 +254,94 @@ def debug_math(x, stream=None):
     _check(lib().casim_debug_math(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(e.data_ptr()),
                                   ctypes.c_void_p(l.data_ptr()), _stream_handle(stream)), "casim_debug_math")
     return e, l
+
+
+# ---- learned surrogate ------------------------------------------------------
+
+def _p(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def rates_dump(state, dz, dt, seed, keep_prob, max_samples, feat, rates, gates, tend, sfc,
+               ncol=None, stream=None):
+    """casim_rates_dump into device tensors feat (>= max x 12 float32), rates,
+    gates (int16).  Returns (written, selected)."""
+    nlev, ld = state.shape[1], state.shape[2]
+    ncol = ld if ncol is None else int(ncol)
+    st = make_state(state, dz, tend, sfc, ld)
+    n = ctypes.c_int64(0)
+    sel = ctypes.c_int64(0)
+    _check(lib().casim_rates_dump(ctypes.byref(st), ncol, nlev, float(dt), int(seed), float(keep_prob),
+                                  int(max_samples), _p(feat), _p(rates), _p(gates), ctypes.byref(n),
+                                  ctypes.byref(sel), _stream_handle(stream)), "casim_rates_dump")
+    return n.value, sel.value
+
+
+def mlp_fit_stats(feat, rates, gates, n, stream=None) -> MlpStats:
+    st = MlpStats()
+    _check(lib().casim_mlp_fit_stats(_p(feat), _p(rates), _p(gates), int(n), ctypes.byref(st),
+                                     _stream_handle(stream)), "casim_mlp_fit_stats")
+    return st
+
+
+def mlp_set_stats(st: MlpStats):
+    _check(lib().casim_mlp_set_stats(ctypes.byref(st)), "casim_mlp_set_stats")
+
+
+def mlp_prepare(feat, rates, gates, n, x, y, m, stream=None):
+    _check(lib().casim_mlp_prepare(_p(feat), _p(rates), _p(gates), int(n), _p(x), _p(y), _p(m),
+                                   _stream_handle(stream)), "casim_mlp_prepare")
+
+
+def mlp_init(seed: int):
+    _check(lib().casim_mlp_init(int(seed)), "casim_mlp_init")
+
+
+def mlp_get_params():
+    import numpy as np
+    out = np.empty(MLP_NPARAMS, dtype=np.float32)
+    _check(lib().casim_mlp_get_params(out.ctypes.data_as(ctypes.c_void_p)), "casim_mlp_get_params")
+    return out
+
+
+def mlp_set_params(theta):
+    import numpy as np
+    t = np.ascontiguousarray(theta, dtype=np.float32)
+    assert t.size == MLP_NPARAMS
+    _check(lib().casim_mlp_set_params(t.ctypes.data_as(ctypes.c_void_p)), "casim_mlp_set_params")
+
+
+def mlp_grad(x, y, m, idx, batch, grad, loss, stream=None):
+    _check(lib().casim_mlp_grad(_p(x), _p(y), _p(m), _p(idx), int(batch), _p(grad), _p(loss),
+                                _stream_handle(stream)), "casim_mlp_grad")
+
+
+def mlp_train_step(x, y, m, idx, batch, lr, loss=None, stream=None):
+    _check(lib().casim_mlp_train_step(_p(x), _p(y), _p(m), _p(idx), int(batch), ctypes.c_float(lr),
+                                      _p(loss), _stream_handle(stream)), "casim_mlp_train_step")
+
+
+def mlp_forward(x, n, y, stream=None):
+    _check(lib().casim_mlp_forward(_p(x), int(n), _p(y), _stream_handle(stream)), "casim_mlp_forward")
+
+
+def mlp_save() -> bytes:
+    size = ctypes.c_size_t(0)
+    _check(lib().casim_mlp_save(None, ctypes.byref(size)), "casim_mlp_save")
+    buf = ctypes.create_string_buffer(size.value)
+    _check(lib().casim_mlp_save(ctypes.cast(buf, ctypes.c_void_p), ctypes.byref(size)), "casim_mlp_save")
+    return buf.raw[:size.value]
+
+
+def mlp_load(blob: bytes):
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(lib().casim_mlp_load(ctypes.cast(buf, ctypes.c_void_p), len(blob)), "casim_mlp_load")
+
+
+def surrogate_load():
+    _check(lib().casim_surrogate_load(), "casim_surrogate_load")
+
+
+def surrogate_infer(feat, gates, n, rates, fallback, stream=None):
+    _check(lib().casim_surrogate_infer(_p(feat), _p(gates), int(n), _p(rates), _p(fallback),
+                                       _stream_handle(stream)), "casim_surrogate_infer")

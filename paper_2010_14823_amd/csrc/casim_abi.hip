@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "casim_internal.h"
+#include "casim_mlp_internal.h"
 
 using namespace casim;
 
@@ -23,6 +24,16 @@ struct Context {
     std::vector<double> h_dz;               // what d_dz holds
     unsigned long long *d_status = nullptr; // 4 counters
     char last_hip[256] = "";
+    // rate-dump scratch: per-block counts and offsets, total
+    int64_t *d_counts = nullptr, *d_offsets = nullptr, *d_total = nullptr;
+    int64_t dump_blocks = 0;
+    // surrogate-step scratch, sized for sur_cap points
+    int32_t *d_idx = nullptr;
+    float *d_feat = nullptr, *d_rates = nullptr;
+    uint16_t *d_gates = nullptr;
+    uint8_t *d_fb = nullptr;
+    unsigned long long *d_count = nullptr;
+    int64_t sur_cap = 0;
 };
 
 Context g;
@@ -130,6 +141,36 @@ int upload_dz(const double *dz, int32_t nlev) {
     return CASIM_OK;
 }
 
+// Grow the surrogate-step scratch to hold npts points (drains the device
+// before freeing buffers a step in flight may use).
+int ensure_sur(int64_t npts) {
+    if (npts <= g.sur_cap) return CASIM_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    hipFree(g.d_idx); hipFree(g.d_feat); hipFree(g.d_rates); hipFree(g.d_gates); hipFree(g.d_fb);
+    g.d_idx = nullptr; g.d_feat = nullptr; g.d_rates = nullptr; g.d_gates = nullptr; g.d_fb = nullptr;
+    g.sur_cap = 0;
+    HIP_TRY(hipMalloc(&g.d_idx, sizeof(int32_t) * npts));
+    HIP_TRY(hipMalloc(&g.d_feat, sizeof(float) * 12 * npts));
+    HIP_TRY(hipMalloc(&g.d_rates, sizeof(float) * 12 * npts));
+    HIP_TRY(hipMalloc(&g.d_gates, sizeof(uint16_t) * npts));
+    HIP_TRY(hipMalloc(&g.d_fb, npts));
+    if (!g.d_count) HIP_TRY(hipMalloc(&g.d_count, sizeof(unsigned long long)));
+    g.sur_cap = npts;
+    return CASIM_OK;
+}
+
+int ensure_dump(int64_t blocks) {
+    if (blocks <= g.dump_blocks) return CASIM_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    hipFree(g.d_counts); hipFree(g.d_offsets);
+    g.d_counts = nullptr; g.d_offsets = nullptr; g.dump_blocks = 0;
+    HIP_TRY(hipMalloc(&g.d_counts, sizeof(int64_t) * blocks));
+    HIP_TRY(hipMalloc(&g.d_offsets, sizeof(int64_t) * blocks));
+    if (!g.d_total) HIP_TRY(hipMalloc(&g.d_total, sizeof(int64_t)));
+    g.dump_blocks = blocks;
+    return CASIM_OK;
+}
+
 int fill_args(const casim_state *s, int64_t ncol, int32_t nlev, double dt, SweepArgs &a) {
     for (int f = 0; f < CASIM_NIN; ++f) a.in[f] = s->in[f];
     for (int f = 0; f < CASIM_NTEND; ++f) a.tend[f] = s->tend[f];
@@ -144,10 +185,21 @@ int fill_args(const casim_state *s, int64_t ncol, int32_t nlev, double dt, Sweep
     a.warm = g.c.warm ? 1 : 0;
     a.newton_iters = g.t.newton_iters;
     a.mode = g.c.mode;
+    a.sur_idx = nullptr;
+    a.sur_rates = nullptr;
+    a.sur_fallback = nullptr;
+    a.sur_f_min = g.t.sur_f_min;
     return CASIM_OK;
 }
 
 }  // namespace
+
+const casim_thresholds *casim_current_thresholds() { return g.init ? &g.t : nullptr; }
+
+int casim_record_hip_error(int code, const char *msg) {
+    snprintf(g.last_hip, sizeof g.last_hip, "HIP error %d: %s", code, msg);
+    return CASIM_EHIP;
+}
 
 extern "C" {
 
@@ -203,7 +255,7 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
         if (!s->sfc[f]) return CASIM_EINVAL;
     for (int k = 0; k < nlev; ++k)
         if (!pos_finite(s->dz[k])) return CASIM_EINVAL;
-    if (g.c.mode == CASIM_MODE_SURROGATE) return CASIM_ENOSURROGATE;
+    if (g.c.mode == CASIM_MODE_SURROGATE && !surrogate_ready()) return CASIM_ENOSURROGATE;
     SweepArgs a{};
     fill_args(s, ncol, nlev, dt, a);
     nsub_of(g.c, s->dz, nlev, dt, a.nsub);
@@ -216,7 +268,67 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
     if (slot > kMaxCarrySlots) return CASIM_ECAPACITY;
     rc = upload_dz(s->dz, nlev);
     if (rc) return rc;
-    HIP_TRY(launch_sweep(g.P, g.fast, a, (hipStream_t)stream));
+    hipStream_t st = (hipStream_t)stream;
+    if (g.c.mode == CASIM_MODE_SURROGATE) {
+        // features and gates of every point that can react -> network -> sweep
+        const int64_t npts = (int64_t)nlev * ncol;
+        if ((rc = ensure_sur(npts))) return rc;
+        HIP_TRY(launch_zero_u64(g.d_count, st));
+        PointArgs pa{};
+        pa.s = a;
+        pa.mode = POINT_SURR;
+        pa.feat = g.d_feat;
+        pa.gates = g.d_gates;
+        pa.idx_map = g.d_idx;
+        pa.counter = g.d_count;
+        HIP_TRY(launch_points(g.P, g.fast, pa, st));
+        HIP_TRY(launch_surrogate_infer(surrogate_dev((float)g.t.sur_range_margin, (float)g.t.sur_maha_max),
+                                       g.d_feat, g.d_gates, npts, g.d_count, g.d_rates, g.d_fb, st));
+        a.sur_idx = g.d_idx;
+        a.sur_rates = g.d_rates;
+        a.sur_fallback = g.d_fb;
+    }
+    HIP_TRY(launch_sweep(g.P, g.fast, a, st));
+    return CASIM_OK;
+}
+
+int casim_rates_dump(const casim_state *s, int64_t ncol, int32_t nlev, double dt, uint64_t seed, double keep_prob,
+                     int64_t max_samples, float *feat, float *rates, uint16_t *gates, int64_t *n_written,
+                     int64_t *n_selected, void *stream) {
+    int rc = check_state(s, ncol, nlev, dt);
+    if (rc) return rc;
+    if (!n_written || !(keep_prob > 0.0 && keep_prob <= 1.0) || max_samples < 0) return CASIM_EINVAL;
+    if (max_samples > 0 && (!feat || !rates || !gates)) return CASIM_EINVAL;
+    *n_written = 0;
+    if (n_selected) *n_selected = 0;
+    if (ncol == 0) return CASIM_OK;
+    const int64_t npts = (int64_t)nlev * ncol;
+    const int64_t blocks = (npts + 255) / 256;
+    if ((rc = ensure_dump(blocks))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    PointArgs pa{};
+    fill_args(s, ncol, nlev, dt, pa.s);
+    pa.s.dz = nullptr;
+    pa.seed = seed;
+    pa.keep = keep_prob;
+    pa.max_out = max_samples;
+    pa.block_counts = g.d_counts;
+    pa.block_offsets = g.d_offsets;
+    pa.feat = feat;
+    pa.rates = rates;
+    pa.gates = gates;
+    pa.mode = POINT_COUNT;
+    HIP_TRY(launch_points(g.P, g.fast, pa, st));
+    HIP_TRY(launch_scan(g.d_counts, blocks, g.d_offsets, g.d_total, st));
+    if (max_samples > 0) {
+        pa.mode = POINT_DUMP;
+        HIP_TRY(launch_points(g.P, g.fast, pa, st));
+    }
+    int64_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, g.d_total, sizeof total, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *n_written = total < max_samples ? total : max_samples;
+    if (n_selected) *n_selected = total;
     return CASIM_OK;
 }
 
@@ -250,6 +362,13 @@ int casim_finalize(void) {
     if (g.d_status) hipFree(g.d_status);
     g.d_dz = nullptr;
     g.d_status = nullptr;
+    hipFree(g.d_counts); hipFree(g.d_offsets); hipFree(g.d_total);
+    g.d_counts = g.d_offsets = g.d_total = nullptr;
+    g.dump_blocks = 0;
+    hipFree(g.d_idx); hipFree(g.d_feat); hipFree(g.d_rates); hipFree(g.d_gates); hipFree(g.d_fb); hipFree(g.d_count);
+    g.d_idx = nullptr; g.d_feat = nullptr; g.d_rates = nullptr; g.d_gates = nullptr; g.d_fb = nullptr;
+    g.d_count = nullptr;
+    g.sur_cap = 0;
     g.h_dz.clear();
     g.init = false;
     g.device = -1;

@@ -107,12 +107,36 @@ struct SweepArgs {
     int32_t stages, warm, newton_iters, mode;
     double dt;
     unsigned long long *status;   // device counters: newton_fail, nonfinite, fallback, inferred
+    // surrogate mode: slot of each point (-1: none), network rates and fallback flags per slot
+    const int32_t *sur_idx;
+    const float *sur_rates;
+    const uint8_t *sur_fallback;
+    double sur_f_min;
 };
+
+// Point-parallel passes over (k, column) in point order p = k*ncol + c.
+struct PointArgs {
+    SweepArgs s;
+    int mode;                      // POINT_COUNT, POINT_DUMP, POINT_SURR
+    uint64_t seed;
+    double keep;
+    int64_t max_out;
+    int64_t *block_counts;         // one per 256-point block
+    const int64_t *block_offsets;
+    float *feat, *rates;
+    uint16_t *gates;
+    int32_t *idx_map;              // surrogate: slot per point
+    unsigned long long *counter;   // surrogate: slots used
+};
+enum { POINT_COUNT = 0, POINT_DUMP = 1, POINT_SURR = 2 };
 
 // Launchers (casim_sweep.hip).  `fast` selects the kernels compiled with
 // kDefaultParams.  Return the launch's hipError_t.
 hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream);
 hipError_t launch_apply(const SweepArgs &a, double dt, hipStream_t stream);
 hipError_t launch_math(const double *x, int64_t n, double *e, double *l, hipStream_t stream);
+hipError_t launch_points(const DevParams &P, bool fast, const PointArgs &pa, hipStream_t stream);
+hipError_t launch_zero_u64(unsigned long long *p, hipStream_t stream);
+hipError_t launch_scan(const int64_t *counts, int64_t n, int64_t *offsets, int64_t *total, hipStream_t stream);
 
 }  // namespace casim

@@ -35,6 +35,7 @@
 // and apply, the sedimentation fluxes, level updates and surface sums.
 #include "casim_internal.h"
 #include "casim_math.h"
+#include "casim_mlp_internal.h"
 
 namespace casim {
 
@@ -331,6 +332,65 @@ __device__ __forceinline__ void apply_rates(const DevParams &P, Pt &w, Pt &d, co
     w.T += dTh; d.T += dTh;
 }
 
+
+// ---- surrogate interface: gates and features of a post-adjustment state ----
+// Bit j is set when rate j's condition holds (the same conditions the plain
+// rates test); bit 12 when the point is supersaturated over ice.
+__device__ __forceinline__ unsigned gate_bits(const DevParams &P, bool warm, const Pt &w, double p, double esl) {
+    const double qmin = P.q_min;
+    const bool cP = w.qc >= qmin, rP = w.qr >= qmin;
+    const bool iP = !warm && w.qi >= qmin, sP = !warm && w.qs >= qmin, gP = !warm && w.qg >= qmin;
+    const bool cold = !warm && w.T < P.T_0, hot = !warm && w.T > P.T_0;
+    unsigned g = 0;
+    if (cP && w.nc > 0.0) g |= 1u << AUTO;
+    if (cP && rP) g |= 1u << ACCR;
+    if (rP && w.qc == 0.0 && w.qv / q_of_e(P, esl, p) - 1.0 < 0.0) g |= 1u << REVP;
+    if (iP && cold) g |= (1u << DEPI);
+    if (sP && cold) g |= (1u << DEPS);
+    if (iP && cold && w.qi > P.q_i0) g |= 1u << IAUT;
+    if (sP && iP && cold) g |= 1u << SACI;
+    if (sP && cP && cold) g |= 1u << SACW;
+    if (gP && cP && cold) g |= 1u << GACW;
+    if (rP && cold) g |= 1u << FRZR;
+    if (sP && hot) g |= 1u << SMLT;
+    if (gP && hot) g |= 1u << GMLT;
+    if (cold && (iP || sP) && w.qv / q_of_e(P, esat_ice(P, w.T), p) - 1.0 > 0.0) g |= CASIM_GATE_SUPERSAT_ICE;
+    return g;
+}
+
+// ln T, ln p, ln rho, ln(q + 1e-12) for v, c; ln(n + 1) for c; (q, n) for r
+// and i; q for s and g.
+__device__ __forceinline__ void features(const Pt &w, double p, double rho, float f[12]) {
+    const double qf = kQFloor;
+    f[0] = (float)log64(w.T);
+    f[1] = (float)log64(p);
+    f[2] = (float)log64(rho);
+    f[3] = (float)log64(w.qv + qf);
+    f[4] = (float)log64(w.qc + qf);
+    f[5] = (float)log64(w.nc + 1.0);
+    f[6] = (float)log64(w.qr + qf);
+    f[7] = (float)log64(w.nr + 1.0);
+    f[8] = (float)log64(w.qi + qf);
+    f[9] = (float)log64(w.ni + 1.0);
+    f[10] = (float)log64(w.qs + qf);
+    f[11] = (float)log64(w.qg + qf);
+}
+
+// Smallest limiter factor min_x min(1, q_x / (R_x dt)) over the source
+// categories for rates r.
+__device__ __forceinline__ double limiter_min_f(const Pt &w, const double r[12], double dt) {
+    const double depi_v = r[DEPI] > 0.0 ? r[DEPI] : 0.0, depi_i = r[DEPI] < 0.0 ? -r[DEPI] : 0.0;
+    const double deps_v = r[DEPS] > 0.0 ? r[DEPS] : 0.0, deps_s = r[DEPS] < 0.0 ? -r[DEPS] : 0.0;
+    const double R[6] = {depi_v + deps_v, r[AUTO] + r[ACCR] + r[SACW] + r[GACW], r[REVP] + r[FRZR],
+                         r[IAUT] + r[SACI] + depi_i, r[SMLT] + deps_s, r[GMLT]};
+    const double q[6] = {w.qv, w.qc, w.qr, w.qi, w.qs, w.qg};
+    double f = 1.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        if (R[c] * dt > q[c]) f = ::fmin(f, q[c] / (R[c] * dt));
+    return f;
+}
+
 // ---- sedimentation of one category over one chunk --------------------------
 // Mass- and number-weighted fall speeds a Gamma(4+b)/6 lambda^-b and
 // a Gamma(1+b) lambda^-b, times (rho_0/rho)^1/2, capped at v_max.
@@ -379,7 +439,7 @@ __device__ __forceinline__ void sediment(const DevParams &P, int cat, int ns, do
     }
 }
 
-template <bool MIX, bool FAST, int C>
+template <bool MIX, bool FAST, int C, bool SUR>
 __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) {
     using R = typename std::conditional<MIX, float, double>::type;
     constexpr int L = kWave / C;
@@ -408,7 +468,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
     for (int j = 0; j < 8; ++j) psurf[j] = 0.0;
     // the lane holding level 0 of its column accumulates and writes the surface sums
     const bool surf_lane = colvalid && g == (a.nlev - 1) % L;
-    unsigned newton_bad = 0, nonfinite = 0;
+    unsigned newton_bad = 0, nonfinite = 0, n_fallback = 0, n_inferred = 0;
 
     for (int k0 = a.nlev - 1; k0 >= 0; k0 -= L) {
         const int k = k0 - g;
@@ -455,9 +515,33 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
             if (do_rates) {
                 // without the adjustment stage the clean-up may still have moved T
                 if (!do_sat && w.T != T_in) es_now = esat_liq(P, w.T);
-                R r[12];
-                rates<R>(P, warm, w, p, rho, ln_rho, rfac, es_now, r);
-                apply_rates<R>(P, w, d, r, dt);
+                bool plain = true;
+                if constexpr (SUR) {
+                    // network rates for this point, unless it falls back
+                    const int slot = a.sur_idx[(int64_t)k * a.ncol + col];
+                    if (slot >= 0) {
+                        bool use = !a.sur_fallback[slot];
+                        if (use) {
+                            const unsigned gb = gate_bits(P, warm, w, p, es_now);
+                            double rr[12];
+#pragma unroll
+                            for (int j = 0; j < 12; ++j)
+                                rr[j] = ((gb >> j) & 1u) ? (double)a.sur_rates[(int64_t)slot * 12 + j] : 0.0;
+                            use = limiter_min_f(w, rr, dt) >= a.sur_f_min;
+                            if (use) {
+                                apply_rates<double>(P, w, d, rr, dt);
+                                plain = false;
+                                ++n_inferred;
+                            }
+                        }
+                        if (!use) ++n_fallback;
+                    }
+                }
+                if (plain) {
+                    R r[12];
+                    rates<R>(P, warm, w, p, rho, ln_rho, rfac, es_now, r);
+                    apply_rates<R>(P, w, d, r, dt);
+                }
             }
         }
         bool out_nz = false;
@@ -493,6 +577,127 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
     }
     if (newton_bad) atomicAdd(&a.status[0], (unsigned long long)newton_bad);
     if (nonfinite) atomicAdd(&a.status[1], (unsigned long long)nonfinite);
+    if (n_fallback) atomicAdd(&a.status[2], (unsigned long long)n_fallback);
+    if (n_inferred) atomicAdd(&a.status[3], (unsigned long long)n_inferred);
+}
+
+// ---- point-parallel passes: rate samples and surrogate inputs -------------
+// One thread per point p = k*ncol + c.  POINT_COUNT counts the points a dump
+// selects per 256-point block; POINT_DUMP writes each selected point's
+// features, plain binary64 rates (as float32) and gate word at its block
+// offset plus its rank in the block (point order, so the output does not
+// depend on scheduling); POINT_SURR computes features and gates of every
+// point where a rate can be non-zero, reserves it a slot and records the slot
+// in idx_map.
+template <bool FAST>
+__global__ __launch_bounds__(256) void point_kernel(DevParams Prt, PointArgs pa) {
+    const DevParams &P = params<FAST>(Prt);
+    const SweepArgs &a = pa.s;
+    __shared__ int wave_cnt[4];
+    const int64_t pid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t npts = (int64_t)a.nlev * a.ncol;
+    const bool valid = pid < npts;
+    const int64_t k = valid ? pid / a.ncol : 0, col = valid ? pid - k * a.ncol : 0;
+    const int64_t ix = k * a.ld + col;
+    const bool warm = a.warm != 0;
+    const bool do_adj = a.stages & CASIM_STAGE_ADJUST, do_sat = a.stages & CASIM_STAGE_SATADJ;
+    Pt w{}, d{};
+    double p = 1.0, rho = 1.0, es_l = 1.0;
+    bool act = false;
+    if (valid) {
+        w.T = a.in[0][ix]; p = a.in[1][ix]; w.qv = a.in[3][ix];
+        w.qc = a.in[4][ix]; w.qr = a.in[6][ix]; w.qi = a.in[8][ix];
+        w.qs = a.in[10][ix]; w.qg = a.in[12][ix];
+        act = (w.qc > 0.0) | (w.qr > 0.0) | (!warm & ((w.qi > 0.0) | (w.qs > 0.0) | (w.qg > 0.0)));
+        es_l = esat_liq(P, w.T);
+        if (!act && do_sat) act = w.qv > q_of_e(P, es_l, p);
+        if (!act && do_adj && !warm && w.T < P.T_nuc) act = w.qv > q_of_e(P, esat_ice(P, w.T), p);
+    }
+    bool sel = act;
+    if (pa.mode != POINT_SURR) sel = act && hash_uniform(pa.seed, (uint64_t)pid) < pa.keep;
+    unsigned g = 0;
+    float f[12];
+    double r[12];
+    if (sel) {
+        rho = a.in[2][ix];
+        w.nc = a.in[5][ix]; w.nr = a.in[7][ix]; w.ni = a.in[9][ix];
+        w.ns = a.in[11][ix]; w.ng = a.in[13][ix];
+        const double T_in = w.T;
+        if (do_adj) adjust(P, warm, w, d, p, rho);
+        double es_now = es_l;
+        if (do_sat) satadj(P, a.newton_iters, w, d, p, T_in, es_l, es_now);
+        if (!do_sat && w.T != T_in) es_now = esat_liq(P, w.T);
+        g = gate_bits(P, warm, w, p, es_now);
+        if (pa.mode == POINT_SURR) sel = (g & 0xFFFu) != 0;
+        if (sel) {
+            features(w, p, rho, f);
+            if (pa.mode == POINT_DUMP)
+                rates<double>(P, warm, w, p, rho, log64(rho), ::sqrt(P.rho_0 / rho), es_now, r);
+        }
+    }
+    // rank of this point among the selected ones of its wave and block
+    const unsigned long long bal = __ballot((int)sel);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int in_wave = __popcll(bal & ((1ull << lane) - 1ull));
+    if (pa.mode == POINT_SURR) {
+        unsigned long long base = 0;
+        if (lane == 0 && bal) base = atomicAdd(pa.counter, (unsigned long long)__popcll(bal));
+        base = __shfl(base, 0);
+        if (valid) pa.idx_map[pid] = sel ? (int32_t)(base + in_wave) : -1;
+        if (sel) {
+            const int64_t slot = (int64_t)(base + in_wave);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) pa.feat[slot * 12 + j] = f[j];
+            pa.gates[slot] = (uint16_t)g;
+        }
+        return;
+    }
+    if (lane == 0) wave_cnt[wv] = __popcll(bal);
+    __syncthreads();
+    if (pa.mode == POINT_COUNT) {
+        if (threadIdx.x == 0) pa.block_counts[blockIdx.x] = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+        return;
+    }
+    int before = 0;
+    for (int j = 0; j < wv; ++j) before += wave_cnt[j];
+    if (sel) {
+        const int64_t pos = pa.block_offsets[blockIdx.x] + before + in_wave;
+        if (pos < pa.max_out) {
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                pa.feat[pos * 12 + j] = f[j];
+                pa.rates[pos * 12 + j] = (float)r[j];
+            }
+            pa.gates[pos] = (uint16_t)g;
+        }
+    }
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p) { *p = 0ull; }
+
+hipError_t launch_zero_u64(unsigned long long *p, hipStream_t stream) {
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, stream, p);
+    return hipGetLastError();
+}
+
+// Exclusive prefix sum of n block counts in one block (fixed order).
+__global__ __launch_bounds__(256) void scan_kernel(const int64_t *counts, int64_t n, int64_t *offsets,
+                                                   int64_t *total) {
+    __shared__ int64_t part[256];
+    const int64_t per = (n + 255) / 256;
+    const int64_t b = threadIdx.x * per, e = b + per < n ? b + per : n;
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += counts[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int j = 0; j < 256; ++j) { const int64_t v = part[j]; part[j] = acc; acc += v; }
+        *total = acc;
+    }
+    __syncthreads();
+    int64_t acc = part[threadIdx.x];
+    for (int64_t i = b; i < e; ++i) { offsets[i] = acc; acc += counts[i]; }
 }
 
 // X += dt * tend for the 12 prognostic fields; q and n clipped at 0.
@@ -518,13 +723,13 @@ int env_int(const char *name, int dflt) {
     return e ? atoi(e) : dflt;
 }
 
-template <bool MIX, bool FAST>
+template <bool MIX, bool FAST, bool SUR>
 hipError_t launch_c(int C, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &P,
                     const SweepArgs &a) {
     switch (C) {
-        case 16: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 16>), grid, block, lds, s, P, a); break;
-        case 32: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 32>), grid, block, lds, s, P, a); break;
-        default: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 64>), grid, block, lds, s, P, a); break;
+        case 16: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 16, SUR>), grid, block, lds, s, P, a); break;
+        case 32: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 32, SUR>), grid, block, lds, s, P, a); break;
+        default: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 64, SUR>), grid, block, lds, s, P, a); break;
     }
     return hipGetLastError();
 }
@@ -552,11 +757,27 @@ hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipSt
     const int64_t waves = (a.ncol + C - 1) / C;
     const int64_t blocks = (waves + wpb - 1) / wpb;
     const dim3 grid((unsigned)blocks), block(wpb * kWave);
-    const bool mix = a.mode == CASIM_MODE_FP32MIX;
-    if (mix) return fast ? launch_c<true, true>(C, grid, block, lds, stream, P, a)
-                         : launch_c<true, false>(C, grid, block, lds, stream, P, a);
-    return fast ? launch_c<false, true>(C, grid, block, lds, stream, P, a)
-                : launch_c<false, false>(C, grid, block, lds, stream, P, a);
+    if (a.mode == CASIM_MODE_FP32MIX)
+        return fast ? launch_c<true, true, false>(C, grid, block, lds, stream, P, a)
+                    : launch_c<true, false, false>(C, grid, block, lds, stream, P, a);
+    if (a.mode == CASIM_MODE_SURROGATE)
+        return fast ? launch_c<false, true, true>(C, grid, block, lds, stream, P, a)
+                    : launch_c<false, false, true>(C, grid, block, lds, stream, P, a);
+    return fast ? launch_c<false, true, false>(C, grid, block, lds, stream, P, a)
+                : launch_c<false, false, false>(C, grid, block, lds, stream, P, a);
+}
+
+hipError_t launch_points(const DevParams &P, bool fast, const PointArgs &pa, hipStream_t stream) {
+    const int64_t npts = (int64_t)pa.s.nlev * pa.s.ncol;
+    const int64_t blocks = (npts + 255) / 256;
+    if (fast) hipLaunchKernelGGL(point_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, stream, P, pa);
+    else hipLaunchKernelGGL(point_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, stream, P, pa);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const int64_t *counts, int64_t n, int64_t *offsets, int64_t *total, hipStream_t stream) {
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(256), 0, stream, counts, n, offsets, total);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void math_kernel(const double *x, int64_t n, double *e, double *l) {

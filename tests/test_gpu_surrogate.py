@@ -1,0 +1,278 @@
+"""The learned surrogate through the C ABI: rate samples against the oracle,
+float32 forward/gradient against the FP64 network oracle, Adam, reproducible
+training and checkpoint resume, bfloat16 matrix-core inference against the
+bfloat16 emulation, surrogate steps (fallback, conservation, non-negativity)
+and what a trained network gains over an untrained one and over zero rates."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from paper_2010_14823_amd import synth
+from util import config_state, field_errors, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dump(key="c0", keep=1.0, cap=100000, seed=3, rows=None, cfg=None):
+    torch = _torch()
+    from paper_2010_14823_amd import casim
+    if cfg is None:
+        cfg, st, dz, _ = config_state(key, rows)
+    else:
+        f, dz, _ = synth.generate(cfg)
+        st = synth.stack(f)
+    dev = torch.from_numpy(st).cuda()
+    nlev, ncol = st.shape[1], st.shape[2]
+    tend = torch.empty((12, nlev, ncol), dtype=torch.float64, device="cuda")
+    sfc = torch.empty((8, ncol), dtype=torch.float64, device="cuda")
+    feat = torch.zeros((cap, 12), dtype=torch.float32, device="cuda")
+    rates = torch.zeros((cap, 12), dtype=torch.float32, device="cuda")
+    gates = torch.zeros((cap,), dtype=torch.int16, device="cuda")
+    casim.init()
+    n, nsel = casim.rates_dump(dev, dz, cfg.dt, seed, keep, cap, feat, rates, gates, tend, sfc)
+    return st, dz, cfg, n, nsel, feat[:n], rates[:n], gates[:n]
+
+
+def test_rates_dump_matches_oracle(oracle_lib):
+    st, dz, cfg, n, nsel, feat, rates, gates = _dump("c0")
+    assert n == nsel and n > 1000
+    f = feat.cpu().numpy(); r = rates.cpu().numpy(); g = gates.cpu().numpy().astype(np.uint16)
+    # rebuild the active points in point order (k*ncol + c) on the host
+    nlev, ncol = st.shape[1], st.shape[2]
+    pts = st.transpose(1, 2, 0).reshape(-1, 14)
+    cond = (pts[:, [4, 6, 8, 10, 12]] > 0).any(axis=1)
+    qsl = np.array([oracle_lib.qsat_liquid(T, p) for T, p in pts[:, :2]])
+    qsi = np.array([oracle_lib.qsat_ice(T, p) for T, p in pts[:, :2]])
+    act = cond | (pts[:, 3] > qsl) | ((pts[:, 0] < 268.15) & (pts[:, 3] > qsi))
+    idx = np.nonzero(act)[0]
+    assert len(idx) == n
+    worst = 0.0
+    for j, pid in enumerate(idx):
+        state, ro = oracle_lib.point_process(pts[pid])
+        den = np.maximum(np.abs(ro), 1e-30)
+        rel = np.abs(r[j] - ro) / den
+        rel[(ro == 0) & (r[j] == 0)] = 0.0
+        worst = max(worst, rel.max())
+        T, qv = state[0], state[1]
+        assert abs(f[j, 0] - np.log(T)) < 1e-5 and abs(f[j, 3] - np.log(qv + 1e-12)) < 1e-5
+    print("dump: %d samples, worst relative rate error %.3g" % (n, worst))
+    assert worst < 1e-6            # float32 storage of binary64 rates
+
+
+def test_rates_dump_sampling_deterministic():
+    a = _dump("c0", keep=0.3, seed=11)
+    b = _dump("c0", keep=0.3, seed=11)
+    c = _dump("c0", keep=0.3, seed=12)
+    assert a[3] == b[3] and 0.2 * a[4] / 0.3 < a[3] < 0.4 * a[4] / 0.3
+    assert np.array_equal(a[5].cpu().numpy(), b[5].cpu().numpy())
+    assert a[3] != c[3] or not np.array_equal(a[5].cpu().numpy(), c[5].cpu().numpy())
+
+
+def _random_net(seed=0, scale=0.15):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(0, scale, omlp.N_PARAMS)).astype(np.float32)
+
+
+def test_forward_and_gradient_match_oracle():
+    torch = _torch()
+    from paper_2010_14823_amd import casim
+    casim.init()
+    theta = _random_net(1)
+    casim.mlp_set_params(theta)
+    rng = np.random.default_rng(2)
+    B = 1000
+    X = rng.normal(size=(B, 12)).astype(np.float32)
+    Y = rng.normal(size=(B, 12)).astype(np.float32)
+    Mk = (rng.uniform(size=(B, 12)) < 0.6).astype(np.float32)
+    x, y, m = (torch.from_numpy(a).cuda() for a in (X, Y, Mk))
+    out = torch.empty((B, 12), dtype=torch.float32, device="cuda")
+    casim.mlp_forward(x, B, out)
+    y64, _ = omlp.forward(theta.astype(np.float64), X.astype(np.float64))
+    yg = out.cpu().numpy()
+    assert np.max(np.abs(yg - y64)) / np.max(np.abs(y64)) < 1e-5
+    grad = torch.empty(casim.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    casim.mlp_grad(x, y, m, None, B, grad, loss)
+    L64, g64 = omlp.loss_and_grad(theta.astype(np.float64), X, Y, Mk)
+    g = grad.cpu().numpy()
+    rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    print("loss %.6g vs %.6g, gradient relative L2 error %.3g" % (loss.item(), L64, rel))
+    assert abs(loss.item() - L64) < 1e-5 * L64
+    assert rel < 1e-4
+    # gathered rows give the same gradient as the equivalent contiguous batch
+    perm = rng.permutation(B).astype(np.int32)[:512]
+    casim.mlp_grad(x, y, m, torch.from_numpy(perm).cuda(), 512, grad, loss)
+    L64p, g64p = omlp.loss_and_grad(theta.astype(np.float64), X[perm], Y[perm], Mk[perm])
+    assert np.linalg.norm(grad.cpu().numpy() - g64p) / np.linalg.norm(g64p) < 1e-4
+
+
+def test_first_adam_step_and_reproducible_resume():
+    torch = _torch()
+    from paper_2010_14823_amd import casim
+    casim.init()
+    rng = np.random.default_rng(5)
+    n = 4096
+    X = torch.from_numpy(rng.normal(size=(n, 12)).astype(np.float32)).cuda()
+    Y = torch.from_numpy(rng.normal(size=(n, 12)).astype(np.float32)).cuda()
+    Mk = torch.from_numpy((rng.uniform(size=(n, 12)) < 0.7).astype(np.float32)).cuda()
+    theta = _random_net(7)
+    casim.mlp_set_params(theta)
+    grad = torch.empty(casim.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    casim.mlp_grad(X, Y, Mk, None, 1024, grad, loss)
+    g = grad.cpu().numpy().astype(np.float64)
+    lr = 1e-3
+    casim.mlp_train_step(X, Y, Mk, None, 1024, lr, loss)
+    t1 = casim.mlp_get_params().astype(np.float64)
+    expect = theta.astype(np.float64) - lr * g / (np.abs(g) + 1e-8)
+    assert np.max(np.abs(t1 - expect)) < 2e-6
+    # reproducibility: same seed and batches -> bitwise identical parameters,
+    # and a checkpoint resumes to the same parameters
+    idx = torch.from_numpy(rng.permutation(n).astype(np.int32)).cuda()
+
+    def run(steps, start=0):
+        for s in range(start, start + steps):
+            casim.mlp_train_step(X, Y, Mk, idx[(s * 512) % 3584:], 512, 1e-3, loss)
+    casim.mlp_init(3)
+    run(6)
+    p_a = casim.mlp_get_params()
+    casim.mlp_init(3)
+    run(3)
+    blob = casim.mlp_save()
+    run(3, 3)
+    p_b = casim.mlp_get_params()
+    casim.mlp_init(99)
+    casim.mlp_load(blob)
+    run(3, 3)
+    p_c = casim.mlp_get_params()
+    assert np.array_equal(p_a, p_b) and np.array_equal(p_a, p_c)
+
+
+def _fit_on_dump(n_epochs=0, key="c0"):
+    """Statistics of a c0 dump; optionally a short training run on it."""
+    torch = _torch()
+    from paper_2010_14823_amd import casim
+    st, dz, cfg, n, nsel, feat, rates, gates = _dump(key)
+    stats = casim.mlp_fit_stats(feat, rates, gates, n)
+    return st, dz, cfg, n, feat, rates, gates, stats
+
+
+def test_inference_matches_bf16_emulation():
+    torch = _torch()
+    from paper_2010_14823_amd import casim
+    st, dz, cfg, n, feat, rates, gates, stats = _fit_on_dump()
+    theta = _random_net(9, 0.1)
+    casim.mlp_set_params(theta)
+    casim.surrogate_load()
+    out = torch.empty((n, 12), dtype=torch.float32, device="cuda")
+    fb = torch.empty((n,), dtype=torch.uint8, device="cuda")
+    casim.surrogate_infer(feat, gates, n, out, fb)
+    r_gpu = out.cpu().numpy()
+    f = feat.cpu().numpy()
+    g = gates.cpu().numpy().astype(np.uint16)
+    xm, xs = np.array(stats.x_mean, np.float32), np.array(stats.x_std, np.float32)
+    ym, ys = np.array(stats.y_mean, np.float32), np.array(stats.y_std, np.float32)
+    z = ((f - xm) / xs).astype(np.float32)
+    y = omlp.forward_bf16(theta, z) * ys + ym
+    r = 1e-12 * np.sinh(y.astype(np.float64))
+    for j in range(12):
+        if j in (3, 4):
+            r[:, j] = np.where(g & (1 << 12), np.abs(r[:, j]), -np.abs(r[:, j]))
+        else:
+            r[:, j] = np.maximum(r[:, j], 0.0)
+        r[:, j] = np.where((g >> j) & 1, r[:, j], 0.0)
+    # compare in the scaled target space where the network works
+    yg = np.arcsinh(r_gpu / 1e-12)
+    ye = np.arcsinh(r / 1e-12)
+    err = np.abs(yg - ye)
+    print("bf16 inference: max |dy| %.3g, 99.9%% %.3g (target scale %.3g)" %
+          (err.max(), np.quantile(err, 0.999), np.abs(ye).max()))
+    assert np.quantile(err, 0.999) < 0.05
+    assert err.max() < 0.5
+    fbn = fb.cpu().numpy()
+    assert fbn.mean() < 0.01          # training points lie inside the trust region
+
+
+def test_all_fallback_reproduces_plain_path(oracle_lib):
+    torch = _torch()
+    from paper_2010_14823_amd import casim
+    st, dz, cfg, n, feat, rates, gates, stats = _fit_on_dump()
+    casim.mlp_set_params(_random_net(4))
+    casim.surrogate_load()
+    c = casim.default_constants(mode=casim.MODE_SURROGATE)
+    t = casim.default_thresholds(sur_maha_max=1e-30)      # every point falls back
+    dev = torch.from_numpy(st).cuda()
+    tend = torch.empty((12,) + st.shape[1:], dtype=torch.float64, device="cuda")
+    sfc = torch.empty((8, st.shape[2]), dtype=torch.float64, device="cuda")
+    casim.init(c, t)
+    casim.status()
+    casim.step(dev, dz, cfg.dt, tend, sfc)
+    s = casim.status()
+    to, so = oracle_lib.step(st, dz, cfg.dt)
+    errs = field_errors(tend.cpu().numpy(), sfc.cpu().numpy(), to, so)
+    print("all-fallback", s, max(errs.values()))
+    assert s["inferred"] == 0 and s["fallback"] > 1000
+    assert max(errs.values()) <= 1e-12
+
+
+def test_surrogate_step_conserves_and_stays_non_negative():
+    torch = _torch()
+    from paper_2010_14823_amd import casim
+    st, dz, cfg, n, feat, rates, gates, stats = _fit_on_dump()
+    casim.mlp_set_params(_random_net(6, 0.2))
+    casim.surrogate_load()
+    c = casim.default_constants(mode=casim.MODE_SURROGATE, stages=7)   # no sedimentation
+    dev = torch.from_numpy(st).cuda()
+    tend = torch.empty((12,) + st.shape[1:], dtype=torch.float64, device="cuda")
+    sfc = torch.empty((8, st.shape[2]), dtype=torch.float64, device="cuda")
+    casim.init(c, casim.default_thresholds())
+    casim.status()
+    casim.step(dev, dz, cfg.dt, tend, sfc)
+    s = casim.status()
+    t = tend.cpu().numpy()
+    assert s["inferred"] > 100
+    dq = t[[1, 2, 4, 6, 8, 10]] * cfg.dt
+    qmax = st[[3, 4, 6, 8, 10, 12]].max(axis=0)
+    assert np.all(np.abs(dq.sum(axis=0)) <= 16 * np.finfo(float).eps * qmax)
+    CP, LV, LS = 1005.0, 2.501e6, 2.834e6
+    resid = CP * t[0] - LV * (t[2] + t[4]) - LS * (t[6] + t[8] + t[10])
+    scale = CP * np.abs(t[0]) + LV * np.abs(t[2] + t[4]) + LS * np.abs(t[6] + t[8] + t[10]) + 1e-30
+    # absolute floor: where processes cancel within one step (e.g. nucleated
+    # ice sublimated again) the net tendencies are pure round-off
+    rel = np.maximum(np.abs(resid) - 1e-14, 0.0) / scale    # 1e-14 J/kg/s: cp * 1e-17 K/s
+    if rel.max() >= 1e-10:
+        k, c = np.unravel_index(np.argmax(rel), rel.shape)
+        print("worst point k=%d c=%d rel %.3g" % (k, c, rel[k, c]))
+        print("  input", st[:, k, c])
+        print("  tend ", t[:, k, c])
+        print("  count of points with rel > 1e-10:", int((rel > 1e-10).sum()))
+    assert np.max(rel) < 1e-10
+    for j, f in enumerate(range(3, 14)):
+        new = st[f] + cfg.dt * t[j + 1]
+        assert np.all(new >= -8 * np.finfo(float).eps * np.maximum(np.abs(st[f]), np.abs(cfg.dt * t[j + 1])))
+
+
+def test_trained_network_beats_untrained_and_zero():
+    """Short training on plain-path samples: the trained network's error on
+    held-out samples is well below an untrained network's and below the
+    zero-rate predictor's (in the standardised target space)."""
+    torch = _torch()
+    from paper_2010_14823_amd import casim, surrogate
+    data = surrogate.generate_samples(seeds=[10, 11], per_seed=60000, log=print)
+    tr = surrogate.Trainer(data, seed=0)
+    untrained = tr.eval_loss(tr.val_idx)
+    # zero-rate predictor: standardised output equal to the standardised asinh(0)
+    y = tr.y.cpu().numpy()[tr.val_idx]
+    m = tr.m.cpu().numpy()[tr.val_idx]
+    y0 = -np.array(tr.stats.y_mean) / np.array(tr.stats.y_std)
+    zero = float(np.sum(m * (y0 - y) ** 2) / np.sum(m))
+    hist = tr.fit(epochs=4, batch=2048, lr=2e-3)
+    trained = hist[-1]["val_loss"]
+    print("validation loss: untrained %.4f, zero predictor %.4f, trained %.4f" % (untrained, zero, trained))
+    assert trained < 0.2 * untrained
+    assert trained < 0.2 * zero
