@@ -59,6 +59,27 @@ def cpu_baseline(st, dz, dt, budget_s=12.0):
                       % (st.shape[2], st.shape[1], len(times), t)}
 
 
+def compare_with_plain(torch, casim, dev, dz, cfg, tend, sfc, mode):
+    """Per-field error of one step of `mode` against one plain binary64 step on
+    the same state, both on the GPU: normwise max|d|/max|plain| and RMS."""
+    casim.step(dev, dz, cfg.dt, tend, sfc)
+    t_mode, s_mode = tend.clone(), sfc.clone()
+    casim.init(casim.default_constants(mode=casim.MODE_FP64))
+    casim.step(dev, dz, cfg.dt, tend, sfc)
+    torch.cuda.synchronize()
+    out = {}
+    names = casim.TEND_NAMES + casim.SFC_NAMES
+    pairs = [(t_mode[j], tend[j]) for j in range(12)] + [(s_mode[j], sfc[j]) for j in range(8)]
+    for name, (a, b) in zip(names, pairs):
+        d = (a - b).abs()
+        den = b.abs().max().item()
+        out[name] = {"max_rel": (d.max().item() / den) if den > 0 else (0.0 if d.max().item() == 0 else None),
+                     "rms_rel": ((d.pow(2).mean().sqrt().item() / b.pow(2).mean().sqrt().item())
+                                 if den > 0 else None)}
+    casim.init(casim.default_constants(mode=mode))
+    return out
+
+
 def copy_probe(torch, nbytes=2 << 30, reps=5):
     """Achieved bandwidth of a plain 2 GiB device-to-device copy (read + write)."""
     a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -82,7 +103,10 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c1")
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32mix"])
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32mix", "surrogate"])
+    ap.add_argument("--checkpoint", default=None, help="surrogate checkpoint (casim_mlp_save blob)")
+    ap.add_argument("--compare", action="store_true",
+                    help="also run one plain binary64 step and report the per-field error of this mode")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--with-copy", action="store_true",
                     help="also time a plain device-to-device copy of 2 GiB (bandwidth reference "
@@ -106,7 +130,14 @@ def main():
     dev = torch.from_numpy(st).cuda()
     tend = torch.empty((12, cfg.nlev, cfg.ncol), dtype=torch.float64, device="cuda")
     sfc = torch.empty((8, cfg.ncol), dtype=torch.float64, device="cuda")
-    mode = casim.MODE_FP64 if args.mode == "fp64" else casim.MODE_FP32MIX
+    mode = {"fp64": casim.MODE_FP64, "fp32mix": casim.MODE_FP32MIX, "surrogate": casim.MODE_SURROGATE}[args.mode]
+    if args.mode == "surrogate":
+        if not args.checkpoint:
+            print("--mode surrogate needs --checkpoint", file=sys.stderr)
+            sys.exit(2)
+        casim.init()
+        casim.mlp_load(open(args.checkpoint, "rb").read())
+        casim.surrogate_load()
     casim.init(casim.default_constants(mode=mode))
     stream = torch.cuda.current_stream()
 
@@ -156,6 +187,11 @@ def main():
         "status": status,
     }
     print("bench: %.4f ms/step on the GPU" % ms_per_step, file=sys.stderr, flush=True)
+    if args.mode == "surrogate":
+        line["surrogate"] = {"fallback_points_per_step": status["fallback"] / args.steps,
+                             "inferred_points_per_step": status["inferred"] / args.steps}
+    if args.compare and args.mode != "fp64":
+        line["error_vs_fp64_plain"] = compare_with_plain(torch, casim, dev, dz, cfg, tend, sfc, mode)
     if args.with_copy:
         line["copy_probe"] = copy_probe(torch)
     if not args.no_cpu:

@@ -86,6 +86,10 @@ def lib():
     """The loaded libcasim.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime under the same soname as ROCm's;
+        # loading torch first makes libcasim bind to that one instance, so
+        # torch's streams and device pointers belong to the library's runtime.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libcasim.so is not built: run python -m paper_2010_14823_amd.build")
         L = ctypes.CDLL(LIB_PATH)

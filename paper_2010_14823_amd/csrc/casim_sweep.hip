@@ -359,21 +359,24 @@ __device__ __forceinline__ unsigned gate_bits(const DevParams &P, bool warm, con
 }
 
 // ln T, ln p, ln rho, ln(q + 1e-12) for v, c; ln(n + 1) for c; (q, n) for r
-// and i; q for s and g.
+// and i; q for s and g.  The features are float32, so the float32 hardware
+// logarithm (v_log_f32, base 2) is accurate enough.
+__device__ __forceinline__ float flog(double x) { return __builtin_amdgcn_logf((float)x) * 0.69314718055994531f; }
+
 __device__ __forceinline__ void features(const Pt &w, double p, double rho, float f[12]) {
     const double qf = kQFloor;
-    f[0] = (float)log64(w.T);
-    f[1] = (float)log64(p);
-    f[2] = (float)log64(rho);
-    f[3] = (float)log64(w.qv + qf);
-    f[4] = (float)log64(w.qc + qf);
-    f[5] = (float)log64(w.nc + 1.0);
-    f[6] = (float)log64(w.qr + qf);
-    f[7] = (float)log64(w.nr + 1.0);
-    f[8] = (float)log64(w.qi + qf);
-    f[9] = (float)log64(w.ni + 1.0);
-    f[10] = (float)log64(w.qs + qf);
-    f[11] = (float)log64(w.qg + qf);
+    f[0] = flog(w.T);
+    f[1] = flog(p);
+    f[2] = flog(rho);
+    f[3] = flog(w.qv + qf);
+    f[4] = flog(w.qc + qf);
+    f[5] = flog(w.nc + 1.0);
+    f[6] = flog(w.qr + qf);
+    f[7] = flog(w.nr + 1.0);
+    f[8] = flog(w.qi + qf);
+    f[9] = flog(w.ni + 1.0);
+    f[10] = flog(w.qs + qf);
+    f[11] = flog(w.qg + qf);
 }
 
 // Smallest limiter factor min_x min(1, q_x / (R_x dt)) over the source

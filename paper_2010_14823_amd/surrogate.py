@@ -8,8 +8,9 @@ in as inputs) and keeps device buffers.
 
 Training set: points where anything can happen, sampled with equal
 probability from LES-like domains (256 x 256 columns x 100 levels, 50 %
-clustered cloud, dt = 2 s) of seeds 10..19, ~400,000 per seed; the last 10 %
-of every seed's samples are held out for validation.
+clustered cloud, dt = 2 s) of seeds 10..19, ~400,000 per seed; a random 10 %
+of the samples (seeded) is held out for validation, and the parameters of
+the epoch with the lowest validation loss are kept.
 """
 from __future__ import annotations
 
@@ -35,7 +36,6 @@ def generate_samples(seeds=range(10, 20), per_seed=400_000, dt=2.0, log=print):
     feat = torch.empty((cap, 12), dtype=torch.float32, device="cuda")
     rates = torch.empty((cap, 12), dtype=torch.float32, device="cuda")
     gates = torch.empty((cap,), dtype=torch.int16, device="cuda")
-    is_val = np.zeros(cap, dtype=bool)
     n = 0
     for s in seeds:
         cfg = training_config(s)
@@ -49,12 +49,11 @@ def generate_samples(seeds=range(10, 20), per_seed=400_000, dt=2.0, log=print):
         keep = min(1.0, per_seed / max(1, n_active))
         got, _ = casim.rates_dump(st, dz, cfg.dt, s, keep, min(per_seed, cap - n), feat[n:], rates[n:],
                                   gates[n:], tend, sfc)
-        nval = got // 10
-        is_val[n + got - nval:n + got] = True
         n += got
         log("surrogate: seed %d -> %d samples (keep %.4f)" % (s, got, keep))
         del st, tend, sfc
-    return {"feat": feat, "rates": rates, "gates": gates, "n": n, "is_val": is_val[:n]}
+    is_val = np.random.default_rng(12345).uniform(size=n) < 0.1
+    return {"feat": feat, "rates": rates, "gates": gates, "n": n, "is_val": is_val}
 
 
 class Trainer:
@@ -91,6 +90,7 @@ class Trainer:
     def fit(self, epochs=10, batch=4096, lr=2e-3, lr_final=1e-4):
         import torch
         hist = []
+        best, best_blob = float("inf"), None
         steps_per_epoch = len(self.train_idx) // batch
         total = epochs * steps_per_epoch
         step = 0
@@ -110,4 +110,43 @@ class Trainer:
             hist.append({"epoch": ep, "train_batch_loss": tl, "val_loss": vl,
                          "seconds": time.perf_counter() - t0})
             self.log("surrogate: epoch %d train %.4f val %.4f (%.1f s)" % (ep, tl, vl, hist[-1]["seconds"]))
+            if vl < best:
+                best, best_blob = vl, casim.mlp_save()
+        if best_blob is not None:
+            casim.mlp_load(best_blob)
+        self.best_val = best
         return hist
+
+
+def main(argv=None):
+    """python -m paper_2010_14823_amd.surrogate --out CKPT [--epochs E] ..."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="train the process-rate surrogate on plain-path samples")
+    ap.add_argument("--out", required=True, help="checkpoint file to write")
+    ap.add_argument("--seeds", default="10-19")
+    ap.add_argument("--per-seed", type=int, default=400_000)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args(argv)
+    lo, hi = (int(x) for x in a.seeds.split("-"))
+    casim.init()
+    t0 = time.perf_counter()
+    data = generate_samples(range(lo, hi + 1), a.per_seed, log=lambda m: print(m, flush=True))
+    t1 = time.perf_counter()
+    tr = Trainer(data, seed=a.seed, log=lambda m: print(m, flush=True))
+    untrained = tr.eval_loss(tr.val_idx)
+    hist = tr.fit(epochs=a.epochs, batch=a.batch, lr=a.lr)
+    t2 = time.perf_counter()
+    blob = casim.mlp_save()
+    with open(a.out, "wb") as f:
+        f.write(blob)
+    print(json.dumps({"samples": data["n"], "train": len(tr.train_idx), "val": len(tr.val_idx),
+                      "untrained_val_loss": untrained, "best_val_loss": tr.best_val, "history": hist,
+                      "sample_seconds": t1 - t0, "train_seconds": t2 - t1}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
