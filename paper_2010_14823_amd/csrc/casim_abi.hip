@@ -259,6 +259,7 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
     SweepArgs a{};
     fill_args(s, ncol, nlev, dt, a);
     nsub_of(g.c, s->dz, nlev, dt, a.nsub);
+    for (int j = 0; j < 4; ++j) a.dts[j] = dt / a.nsub[j];
     int slot = 0;
     for (int j = 0; j < 4; ++j) {
         a.slot0[j] = slot;

@@ -106,6 +106,7 @@ struct SweepArgs {
     int32_t nlev, nsub[4], slot0[4], nslots;
     int32_t stages, warm, newton_iters, mode;
     double dt;
+    double dts[4];             // dt / nsub per category
     unsigned long long *status;   // device counters: newton_fail, nonfinite, fallback, inferred
     // surrogate mode: slot of each point (-1: none), network rates and fallback flags per slot
     const int32_t *sur_idx;

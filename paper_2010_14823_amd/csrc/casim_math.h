@@ -52,7 +52,10 @@ __device__ __forceinline__ double log64(double x) {
     int e = __builtin_amdgcn_frexp_exp(x);             // x = m 2^e, m in [0.5, 1)
     double m = __builtin_amdgcn_frexp_mant(x);
     if (m < 0.70710678118654752440) { m *= 2.0; e -= 1; }
-    const double s = (m - 1.0) / (m + 1.0);
+    double rm = __builtin_amdgcn_rcp(m + 1.0);              // 1/(m+1), refined twice
+    rm = __builtin_fma(rm, __builtin_fma(-(m + 1.0), rm, 1.0), rm);
+    rm = __builtin_fma(rm, __builtin_fma(-(m + 1.0), rm, 1.0), rm);
+    const double s = (m - 1.0) * rm;
     const double z = s * s;
     // sum_{j=0}^{10} z^j / (2j+1)
     double q = 1.0 / 21.0;
@@ -70,6 +73,18 @@ __device__ __forceinline__ double log64(double x) {
     const double lm = 2.0 * s * q;
     const double r = __builtin_fma(ed, ln2_hi, __builtin_fma(ed, ln2_lo, lm));
     return x == 0.0 ? -__builtin_inf() : r;
+}
+
+// 1/x for positive, finite, normal x: the hardware reciprocal estimate
+// refined by two Newton-Raphson steps r <- r + r (1 - x r) (within about one
+// ulp; no special-case handling, which the IEEE division sequence spends
+// most of its instructions on).
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
 }
 
 }  // namespace casim

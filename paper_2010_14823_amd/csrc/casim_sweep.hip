@@ -63,6 +63,10 @@ template <> struct Mth<float> {
 template <class R>
 __device__ __forceinline__ R clampv(R x, R lo, R hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
+// a / b in the rate precision: reciprocal-based in binary64, plain in binary32
+__device__ __forceinline__ double rdiv(double a, double b) { return a * rcp64(b); }
+__device__ __forceinline__ float rdiv(float a, float b) { return a / b; }
+
 // Working state of one point: values (w) and accumulated increments (d).
 struct Pt {
     double T, qv, qc, nc, qr, nr, qi, ni, qs, ns, qg, ng;
@@ -73,14 +77,14 @@ struct Pt {
 // expression so a value computed once can be reused for the same T.
 __device__ __forceinline__ double esat_liq(const DevParams &P, double T) {
     const double Tc = T - P.T_0;
-    return P.esl_a * exp64(P.esl_b * Tc * (1.0 / (Tc + P.esl_c)));
+    return P.esl_a * exp64(P.esl_b * Tc * rcp64(Tc + P.esl_c));
 }
 __device__ __forceinline__ double esat_ice(const DevParams &P, double T) {
     const double Tc = T - P.T_0;
-    return P.esi_a * exp64(P.esi_b * Tc * (1.0 / (Tc + P.esi_c)));
+    return P.esi_a * exp64(P.esi_b * Tc * rcp64(Tc + P.esi_c));
 }
 __device__ __forceinline__ double q_of_e(const DevParams &P, double e, double p) {
-    return P.eps * e / (p - P.one_m_eps * e);
+    return P.eps * e * rcp64(p - P.one_m_eps * e);
 }
 
 // ---- clean-up and instant phase changes ----------------------------------
@@ -120,7 +124,7 @@ __device__ __forceinline__ void adjust(const DevParams &P, bool warm, Pt &w, Pt 
     if (w.T < P.T_nuc) {                          // Cooper (1986) nucleation
         double qsi = q_of_e(P, esat_ice(P, w.T), p);
         if (w.qv > qsi) {
-            double nin = ::fmin(P.cooper_a * exp64(P.cooper_b * (P.T_0 - w.T)), P.cooper_max) / rho;
+            double nin = ::fmin(P.cooper_a * exp64(P.cooper_b * (P.T_0 - w.T)), P.cooper_max) * rcp64(rho);
             if (nin > w.ni) {
                 double dn = nin - w.ni;
                 double dq = ::fmin(dn * P.m_i0, w.qv - qsi);
@@ -146,19 +150,19 @@ __device__ __forceinline__ bool satadj(const DevParams &P, int iters, Pt &w, Pt 
     double delta = 0.0, es = es0;
     for (int it = 0; it < iters; ++it) {
         const double Tc = (w.T + delta) - P.T_0;
-        const double rtc = 1.0 / (Tc + P.esl_c);
+        const double rtc = rcp64(Tc + P.esl_c);
         if (it > 0) es = P.esl_a * exp64(P.esl_b * Tc * rtc);
-        const double rden = 1.0 / (p - P.one_m_eps * es);
+        const double rden = rcp64(p - P.one_m_eps * es);
         const double qs = P.eps * es * rden;
         const double f = P.cp * delta - P.L_v * (w.qv - qs);
         const double fp = P.cp + P.L_v * qs * (p * rden) * P.esl_bc * (rtc * rtc);
-        delta -= f / fp;
+        delta -= f * rcp64(fp);
     }
     const double T1 = w.T + delta;
     const double es1 = esat_liq(P, T1);
     const double qs1 = q_of_e(P, es1, p);
-    const bool bad = !(::fabs(P.cp * delta - P.L_v * (w.qv - qs1)) / (P.L_v * qs1) <= P.newton_rtol);
-    const double dq = P.cp * delta / P.L_v;
+    const bool bad = !(::fabs(P.cp * delta - P.L_v * (w.qv - qs1)) <= P.newton_rtol * (P.L_v * qs1));
+    const double dq = P.cp * delta * (1.0 / P.L_v);
     if (w.qc + dq >= 0.0) {
         const bool newcloud = (w.qc == 0.0 && dq > 0.0);
         w.qc += dq; d.qc += dq;
@@ -200,11 +204,11 @@ __device__ __forceinline__ void rates(const DevParams &P, bool warm, const Pt &w
     const bool revp = rP && w.qc == 0.0;
     const bool dep = cold && (iP || sP);
     // saturation ratios in binary64
-    const double Sl_m1 = w.qv / q_of_e(P, esl, p) - 1.0;
+    const double Sl_m1 = w.qv * rcp64(q_of_e(P, esl, p)) - 1.0;
     double esi = 0.0, Si_m1 = 0.0;
     if (dep) {
         esi = esat_ice(P, w.T);
-        Si_m1 = w.qv / q_of_e(P, esi, p) - 1.0;
+        Si_m1 = w.qv * rcp64(q_of_e(P, esi, p)) - 1.0;
     }
 
     const R T = R(w.T), rh = R(rho), lrh = R(ln_rho), rf = R(rfac);
@@ -220,7 +224,7 @@ __device__ __forceinline__ void rates(const DevParams &P, bool warm, const Pt &w
         ilr = M::exp(-llr);
     }
     if (iP && cold) {
-        const R lli = clampv((R(P.ln_lam_coef[1]) + M::log(R(w.ni) / R(w.qi))) * R(1.0 / 3.0),
+        const R lli = clampv((R(P.ln_lam_coef[1]) + M::log(rdiv(R(w.ni), R(w.qi)))) * R(1.0 / 3.0),
                              R(P.ln_lam_lo[1]), R(P.ln_lam_hi[1]));
         ili = M::exp(-lli);
     }
@@ -241,15 +245,15 @@ __device__ __forceinline__ void rates(const DevParams &P, bool warm, const Pt &w
     const bool do_revp = revp && Sl_m1 < 0.0;
     if (do_revp || dep) {
         const R KRT2 = R(P.K_a) * R(P.R_v) * T * T;
-        const R Dv = R(P.Dv0) * M::exp(R(P.Dv_exp) * M::log(T * R(1.0 / P.T_0))) * (R(1e5) / R(p));
+        const R Dv = R(P.Dv0) * M::exp(R(P.Dv_exp) * M::log(T * R(1.0 / P.T_0))) * rdiv(R(1e5), R(p));
         if (do_revp) {
-            const R Gl = R(1) / (R(P.L_v) * R(P.L_v) / KRT2 + R(P.R_v) * T / (Dv * R(esl)));
+            const R Gl = rdiv(R(1), rdiv(R(P.L_v) * R(P.L_v), KRT2) + rdiv(R(P.R_v) * T, Dv * R(esl)));
             r[REVP] = R(P.two_pi) * Gl * R(-Sl_m1) * R(w.nr) * ilr;
         }
         if (dep) {
-            const R Gi = R(1) / (R(P.L_s) * R(P.L_s) / KRT2 + R(P.R_v) * T / (Dv * R(esi)));
+            const R Gi = rdiv(R(1), rdiv(R(P.L_s) * R(P.L_s), KRT2) + rdiv(R(P.R_v) * T, Dv * R(esi)));
             if (iP) r[DEPI] = R(P.two_pi) * Gi * R(Si_m1) * R(w.ni) * ili;
-            if (sP) r[DEPS] = R(P.two_pi) * Gi * R(Si_m1) * R(P.N0_s) / rh * (ils * ils);
+            if (sP) r[DEPS] = rdiv(R(P.two_pi) * Gi * R(Si_m1) * R(P.N0_s), rh) * (ils * ils);
         }
     }
     if (cold) {
@@ -268,7 +272,7 @@ __device__ __forceinline__ void rates(const DevParams &P, bool warm, const Pt &w
         }
     }
     if (hot && (sP || gP)) {
-        const R melt = R(P.two_pi) * R(P.K_a) * dT0 / (rh * R(P.L_f));
+        const R melt = rdiv(R(P.two_pi) * R(P.K_a) * dT0, rh * R(P.L_f));
         if (sP) r[SMLT] = melt * R(P.N0_s) * (ils * ils);
         if (gP) r[GMLT] = melt * R(P.N0_g) * (ilg * ilg);
     }
@@ -290,20 +294,20 @@ __device__ __forceinline__ void apply_rates(const DevParams &P, Pt &w, Pt &d, co
     const double Rg = r[GMLT];
     const bool lv = Rv * dt > w.qv, lc = Rc * dt > w.qc, lr = Rr * dt > w.qr;
     const bool li = Ri * dt > w.qi, ls = Rs * dt > w.qs, lg = Rg * dt > w.qg;
-    const double fv = lv ? w.qv / (Rv * dt) : 1.0, fc = lc ? w.qc / (Rc * dt) : 1.0;
-    const double fr = lr ? w.qr / (Rr * dt) : 1.0, fi = li ? w.qi / (Ri * dt) : 1.0;
-    const double fs = ls ? w.qs / (Rs * dt) : 1.0, fg = lg ? w.qg / (Rg * dt) : 1.0;
+    const double fv = lv ? w.qv * rcp64(Rv * dt) : 1.0, fc = lc ? w.qc * rcp64(Rc * dt) : 1.0;
+    const double fr = lr ? w.qr * rcp64(Rr * dt) : 1.0, fi = li ? w.qi * rcp64(Ri * dt) : 1.0;
+    const double fs = ls ? w.qs * rcp64(Rs * dt) : 1.0, fg = lg ? w.qg * rcp64(Rg * dt) : 1.0;
     const double auto_ = r[AUTO] * fc, accr = r[ACCR] * fc, sacw = r[SACW] * fc, gacw = r[GACW] * fc;
     const double revp = r[REVP] * fr, frzr = r[FRZR] * fr;
     const double iaut = r[IAUT] * fi, saci = r[SACI] * fi;
     const double smlt = r[SMLT] * fs, gmlt = r[GMLT] * fg;
     depi_v *= fv; deps_v *= fv; depi_i *= fi; deps_s *= fs;
 
-    const double mm_c = w.qc > 0.0 ? w.nc / w.qc : 0.0;
-    const double mm_r = w.qr > 0.0 ? w.nr / w.qr : 0.0;
-    const double mm_i = w.qi > 0.0 ? w.ni / w.qi : 0.0;
-    const double mm_s = w.qs > 0.0 ? w.ns / w.qs : 0.0;
-    const double mm_g = w.qg > 0.0 ? w.ng / w.qg : 0.0;
+    const double mm_c = w.qc > 0.0 ? w.nc * rcp64(w.qc) : 0.0;
+    const double mm_r = w.qr > 0.0 ? w.nr * rcp64(w.qr) : 0.0;
+    const double mm_i = w.qi > 0.0 ? w.ni * rcp64(w.qi) : 0.0;
+    const double mm_s = w.qs > 0.0 ? w.ns * rcp64(w.qs) : 0.0;
+    const double mm_g = w.qg > 0.0 ? w.ng * rcp64(w.qg) : 0.0;
 
     const double sq_v = dt * (depi_v + deps_v), g_v = dt * (revp + depi_i + deps_s);
     const double sq_c = dt * (auto_ + accr + sacw + gacw);
@@ -344,7 +348,7 @@ __device__ __forceinline__ unsigned gate_bits(const DevParams &P, bool warm, con
     unsigned g = 0;
     if (cP && w.nc > 0.0) g |= 1u << AUTO;
     if (cP && rP) g |= 1u << ACCR;
-    if (rP && w.qc == 0.0 && w.qv / q_of_e(P, esl, p) - 1.0 < 0.0) g |= 1u << REVP;
+    if (rP && w.qc == 0.0 && w.qv * rcp64(q_of_e(P, esl, p)) - 1.0 < 0.0) g |= 1u << REVP;
     if (iP && cold) g |= (1u << DEPI);
     if (sP && cold) g |= (1u << DEPS);
     if (iP && cold && w.qi > P.q_i0) g |= 1u << IAUT;
@@ -354,7 +358,7 @@ __device__ __forceinline__ unsigned gate_bits(const DevParams &P, bool warm, con
     if (rP && cold) g |= 1u << FRZR;
     if (sP && hot) g |= 1u << SMLT;
     if (gP && hot) g |= 1u << GMLT;
-    if (cold && (iP || sP) && w.qv / q_of_e(P, esat_ice(P, w.T), p) - 1.0 > 0.0) g |= CASIM_GATE_SUPERSAT_ICE;
+    if (cold && (iP || sP) && w.qv * rcp64(q_of_e(P, esat_ice(P, w.T), p)) - 1.0 > 0.0) g |= CASIM_GATE_SUPERSAT_ICE;
     return g;
 }
 
@@ -390,7 +394,7 @@ __device__ __forceinline__ double limiter_min_f(const Pt &w, const double r[12],
     double f = 1.0;
 #pragma unroll
     for (int c = 0; c < 6; ++c)
-        if (R[c] * dt > q[c]) f = ::fmin(f, q[c] / (R[c] * dt));
+        if (R[c] * dt > q[c]) f = ::fmin(f, q[c] * rcp64(R[c] * dt));
     return f;
 }
 
@@ -401,7 +405,7 @@ template <class R, int C>
 __device__ __forceinline__ void sediment(const DevParams &P, int cat, int ns, double dts, double *lds,
                                          int g, int c, bool need, double rho, double ln_rho, double rfac,
                                          double inv_rdz, bool surf, double &q, double &n, double &dq,
-                                         double &dn, double &psq, double &psn, bool &out_nz) {
+                                         double &dn, double *psq, double *psn, bool &out_nz) {
     using M = Mth<R>;
     constexpr int L = kWave / C;
     double *cq = lds;                 // [s][c] flux of mass leaving the previous chunk
@@ -412,7 +416,7 @@ __device__ __forceinline__ void sediment(const DevParams &P, int cat, int ns, do
         double Fq = 0.0, Fn = 0.0;
         if (need && q >= P.q_min) {
             R ll;
-            if (cat < 2) ll = (ln_coef + M::log(R(n) / R(q))) * R(1.0 / 3.0);
+            if (cat < 2) ll = (ln_coef + M::log(rdiv(R(n), R(q)))) * R(1.0 / 3.0);
             else         ll = (ln_coef - R(ln_rho) - M::log(R(q))) * R(0.25);
             ll = clampv(ll, lo, hi);
             const R e = M::exp(mb * ll) * R(rfac);
@@ -438,7 +442,7 @@ __device__ __forceinline__ void sediment(const DevParams &P, int cat, int ns, do
         }
         if (g == L - 1) { cq[s * C + c] = Fq; cn[s * C + c] = Fn; }
         out_nz |= (Fq != 0.0) | (Fn != 0.0);
-        if (surf) { psq += Fq * dts; psn += Fn * dts; }
+        if (surf) { *psq += Fq * dts; *psn += Fn * dts; }
     }
 }
 
@@ -451,7 +455,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
     const int lane = threadIdx.x & (kWave - 1);
     const int wib = threadIdx.x / kWave;
     const int g = lane / C, c = lane % C;
-    double *lds = lds_all + (size_t)wib * a.nslots * C;
+    double *lds = lds_all + (size_t)wib * (a.nslots + 8) * C;
     const int64_t col = ((int64_t)blockIdx.x * (blockDim.x / kWave) + wib) * C + c;
     const bool colvalid = col < a.ncol;
     const double dt = a.dt, inv_dt = 1.0 / dt;
@@ -459,31 +463,54 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
     const int ncat = warm ? 1 : 4;
     const bool do_adj = a.stages & CASIM_STAGE_ADJUST, do_sat = a.stages & CASIM_STAGE_SATADJ;
     const bool do_rates = a.stages & CASIM_STAGE_RATES, do_sed = a.stages & CASIM_STAGE_SED;
-    double dts[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) dts[j] = dt / a.nsub[j];
 
-    for (int j = lane; j < a.nslots * C; j += kWave) lds[j] = 0.0;
+    for (int j = lane; j < (a.nslots + 8) * C; j += kWave) lds[j] = 0.0;
     unsigned long long carry_cols = 0;   // bit c: a flux enters column c's next chunk from above
     const unsigned long long cmask = (C == 64) ? ~0ull : ((1ull << C) - 1ull);
-    double psurf[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) psurf[j] = 0.0;
+    // surface sums of the wave's columns, [8][C] in LDS after the carries
+    double *psurf = lds + (size_t)a.nslots * C + c;
     // the lane holding level 0 of its column accumulates and writes the surface sums
     const bool surf_lane = colvalid && g == (a.nlev - 1) % L;
     unsigned newton_bad = 0, nonfinite = 0, n_fallback = 0, n_inferred = 0;
+
+    // Every field of the next chunk is loaded while the current one is
+    // processed: the 8 that decide activity for all lanes, the other 6 for
+    // lanes whose column was busy in this chunk (the next chunk of a busy
+    // column is usually busy too).  A lane that turns busy without them loads
+    // them itself.  Loading ahead keeps a chunk from waiting on the previous
+    // chunk's stores, which share the vector-memory counter with loads.
+    struct Ahead { double T, p, qv, qc, qr, qi, qs, qg, rho, nc, nr, ni, ns, ng; bool extra; };
+    auto load_ahead = [&](int kk0, bool extra) {
+        Ahead v{0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, false};
+        const int kk = kk0 - g;
+        if (colvalid && kk >= 0) {
+            const int64_t jx = (int64_t)kk * a.ld + col;
+            v.T = a.in[0][jx]; v.p = a.in[1][jx]; v.qv = a.in[3][jx];
+            v.qc = a.in[4][jx]; v.qr = a.in[6][jx]; v.qi = a.in[8][jx];
+            v.qs = a.in[10][jx]; v.qg = a.in[12][jx];
+            if (extra) {
+                v.rho = a.in[2][jx];
+                v.nc = a.in[5][jx]; v.nr = a.in[7][jx]; v.ni = a.in[9][jx];
+                v.ns = a.in[11][jx]; v.ng = a.in[13][jx];
+                v.extra = true;
+            }
+        }
+        return v;
+    };
+    Ahead nxt = load_ahead(a.nlev - 1, false);
 
     for (int k0 = a.nlev - 1; k0 >= 0; k0 -= L) {
         const int k = k0 - g;
         const bool vp = colvalid && k >= 0;
         const int64_t ix = (int64_t)(k < 0 ? 0 : k) * a.ld + col;
+        const Ahead cur = nxt;
         Pt w{}, d{};
         double p = 1.0, rho = 1.0, es_l = 1.0;
         bool act = false;
         if (vp) {
-            w.T = a.in[0][ix]; p = a.in[1][ix]; w.qv = a.in[3][ix];
-            w.qc = a.in[4][ix]; w.qr = a.in[6][ix]; w.qi = a.in[8][ix];
-            w.qs = a.in[10][ix]; w.qg = a.in[12][ix];
+            w.T = cur.T; p = cur.p; w.qv = cur.qv;
+            w.qc = cur.qc; w.qr = cur.qr; w.qi = cur.qi;
+            w.qs = cur.qs; w.qg = cur.qg;
             act = (w.qc > 0.0) | (w.qr > 0.0) | (!warm & ((w.qi > 0.0) | (w.qs > 0.0) | (w.qg > 0.0)));
             es_l = esat_liq(P, w.T);
             // a condensate-free point changes only if supersaturated
@@ -493,6 +520,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
         const double T_in = w.T;
         const unsigned long long bal = __ballot((int)act);
         if (bal == 0ull && carry_cols == 0ull) {
+            nxt = load_ahead(k0 - L, false);
             if (vp) {
 #pragma unroll
                 for (int f = 0; f < CASIM_NTEND; ++f) a.tend[f][ix] = 0.0;
@@ -502,15 +530,22 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
         unsigned long long colbits = carry_cols;
 #pragma unroll
         for (int gg = 0; gg < L; ++gg) colbits |= (bal >> (gg * C)) & cmask;
-        const bool need = vp && (act || ((colbits >> c) & 1ull));
+        const bool col_busy = (colbits >> c) & 1ull;
+        const bool need = vp && (act || col_busy);
         double ln_rho = 0.0;
         if (need) {
-            rho = a.in[2][ix];
-            w.nc = a.in[5][ix]; w.nr = a.in[7][ix]; w.ni = a.in[9][ix];
-            w.ns = a.in[11][ix]; w.ng = a.in[13][ix];
-            ln_rho = log64(rho);
+            if (cur.extra) {
+                rho = cur.rho;
+                w.nc = cur.nc; w.nr = cur.nr; w.ni = cur.ni; w.ns = cur.ns; w.ng = cur.ng;
+            } else {
+                rho = a.in[2][ix];
+                w.nc = a.in[5][ix]; w.nr = a.in[7][ix]; w.ni = a.in[9][ix];
+                w.ns = a.in[11][ix]; w.ng = a.in[13][ix];
+            }
         }
-        const double rfac = ::sqrt(P.rho_0 / rho);
+        nxt = load_ahead(k0 - L, col_busy);
+        if (need) ln_rho = log64(rho);
+        const double rfac = ::sqrt(P.rho_0 * rcp64(rho));
         if (act) {
             if (do_adj) adjust(P, warm, w, d, p, rho);
             double es_now = es_l;
@@ -550,17 +585,17 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
         bool out_nz = false;
         if (do_sed) {
             double inv_rdz = 0.0;
-            if (need) inv_rdz = 1.0 / (rho * a.dz[k < 0 ? 0 : k]);
+            if (need) inv_rdz = rcp64(rho * a.dz[k < 0 ? 0 : k]);
             const bool surf = vp && k == 0;
-            sediment<R, C>(P, 0, a.nsub[0], dts[0], lds + a.slot0[0] * C, g, c, need, rho, ln_rho, rfac,
-                           inv_rdz, surf, w.qr, w.nr, d.qr, d.nr, psurf[0], psurf[4], out_nz);
+            sediment<R, C>(P, 0, a.nsub[0], a.dts[0], lds + a.slot0[0] * C, g, c, need, rho, ln_rho, rfac,
+                           inv_rdz, surf, w.qr, w.nr, d.qr, d.nr, psurf + 0 * C, psurf + 4 * C, out_nz);
             if (ncat > 1) {
-                sediment<R, C>(P, 1, a.nsub[1], dts[1], lds + a.slot0[1] * C, g, c, need, rho, ln_rho, rfac,
-                               inv_rdz, surf, w.qi, w.ni, d.qi, d.ni, psurf[1], psurf[5], out_nz);
-                sediment<R, C>(P, 2, a.nsub[2], dts[2], lds + a.slot0[2] * C, g, c, need, rho, ln_rho, rfac,
-                               inv_rdz, surf, w.qs, w.ns, d.qs, d.ns, psurf[2], psurf[6], out_nz);
-                sediment<R, C>(P, 3, a.nsub[3], dts[3], lds + a.slot0[3] * C, g, c, need, rho, ln_rho, rfac,
-                               inv_rdz, surf, w.qg, w.ng, d.qg, d.ng, psurf[3], psurf[7], out_nz);
+                sediment<R, C>(P, 1, a.nsub[1], a.dts[1], lds + a.slot0[1] * C, g, c, need, rho, ln_rho, rfac,
+                               inv_rdz, surf, w.qi, w.ni, d.qi, d.ni, psurf + 1 * C, psurf + 5 * C, out_nz);
+                sediment<R, C>(P, 2, a.nsub[2], a.dts[2], lds + a.slot0[2] * C, g, c, need, rho, ln_rho, rfac,
+                               inv_rdz, surf, w.qs, w.ns, d.qs, d.ns, psurf + 2 * C, psurf + 6 * C, out_nz);
+                sediment<R, C>(P, 3, a.nsub[3], a.dts[3], lds + a.slot0[3] * C, g, c, need, rho, ln_rho, rfac,
+                               inv_rdz, surf, w.qg, w.ng, d.qg, d.ng, psurf + 3 * C, psurf + 7 * C, out_nz);
             }
         }
         carry_cols = (__ballot((int)(g == L - 1 && out_nz)) >> ((L - 1) * C)) & cmask;
@@ -576,7 +611,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
     }
     if (surf_lane) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) a.sfc[j][col] = psurf[j];
+        for (int j = 0; j < 8; ++j) a.sfc[j][col] = psurf[j * C];
     }
     if (newton_bad) atomicAdd(&a.status[0], (unsigned long long)newton_bad);
     if (nonfinite) atomicAdd(&a.status[1], (unsigned long long)nonfinite);
@@ -730,6 +765,8 @@ template <bool MIX, bool FAST, bool SUR>
 hipError_t launch_c(int C, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &P,
                     const SweepArgs &a) {
     switch (C) {
+        case 4: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 4, SUR>), grid, block, lds, s, P, a); break;
+        case 8: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 8, SUR>), grid, block, lds, s, P, a); break;
         case 16: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 16, SUR>), grid, block, lds, s, P, a); break;
         case 32: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 32, SUR>), grid, block, lds, s, P, a); break;
         default: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 64, SUR>), grid, block, lds, s, P, a); break;
@@ -739,23 +776,26 @@ hipError_t launch_c(int C, dim3 grid, dim3 block, size_t lds, hipStream_t s, con
 
 }  // namespace
 
-// Columns per wavefront: enough wavefronts to give every SIMD of the chip
-// (256 CUs x 4) several to interleave, without giving up full 128-byte rows.
+// Columns per wavefront.  16-column tiles (16 x 4 levels, one 128-byte row
+// per level) measured best on the large domains; narrower tiles keep at
+// least 2048 wavefronts (two per SIMD) on small ones.
 static int pick_columns_per_wave(int64_t ncol) {
     const int forced = env_int("CASIM_COLS_PER_WAVE", 0);
-    if (forced == 16 || forced == 32 || forced == 64) return forced;
-    const int64_t target_waves = 4096;
-    if (ncol / 64 >= target_waves) return 64;
-    if (ncol / 32 >= target_waves) return 32;
-    return 16;
+    if (forced == 4 || forced == 8 || forced == 16 || forced == 32 || forced == 64) return forced;
+    if (ncol / 16 >= 2048) return 16;
+    if (ncol / 8 >= 2048) return 8;
+    return 4;
 }
 
 hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream) {
     const int C = pick_columns_per_wave(a.ncol);
-    int wpb = env_int("CASIM_WAVES_PER_BLOCK", 1);
+    // narrow tiles: enough wavefronts per block to cover whole 128-byte rows,
+    // so the halves of a line are fetched by one CU
+    int wpb = env_int("CASIM_WAVES_PER_BLOCK", C >= 16 ? 1 : 16 / C);
     if (wpb < 1 || wpb > 4) wpb = 1;
-    size_t lds = (size_t)wpb * a.nslots * C * sizeof(double);
-    while (wpb > 1 && lds > 65536) { --wpb; lds = (size_t)wpb * a.nslots * C * sizeof(double); }
+    const size_t per_wave = (size_t)(a.nslots + 8) * C * sizeof(double);   // carries + surface sums
+    size_t lds = (size_t)wpb * per_wave;
+    while (wpb > 1 && lds > 65536) { --wpb; lds = (size_t)wpb * per_wave; }
     if (lds > 65536) return hipErrorInvalidValue;
     const int64_t waves = (a.ncol + C - 1) / C;
     const int64_t blocks = (waves + wpb - 1) / wpb;

@@ -166,7 +166,7 @@ def test_argument_errors_on_device():
     assert casim.lib().casim_step(st, 2, 600, 2.0, None) == -1
 
 
-@pytest.mark.parametrize("cols_per_wave", [16, 32, 64])
+@pytest.mark.parametrize("cols_per_wave", [4, 8, 16, 32, 64])
 @pytest.mark.parametrize("generic", [False, True])
 def test_tile_widths_and_runtime_constants(oracle_lib, cols_per_wave, generic, monkeypatch):
     """Every wavefront tile (C columns x 64/C levels) and both the compiled-in
