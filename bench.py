@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+KERNEL_SOURCES = ["casim_sweep.hip", "casim_internal.h", "casim_math.h", "casim_defaults.h"]
 B_CLOUDY, B_CLEAR, B_COLUMN = 208, 160, 64   # algorithmic bytes per point / column
 
 
@@ -36,6 +38,35 @@ def algorithmic_bytes(cfg, mask) -> int:
     ncloudy = int(mask.sum())
     nclear = cfg.ncol - ncloudy
     return cfg.nlev * (ncloudy * B_CLOUDY + nclear * B_CLEAR) + cfg.ncol * B_COLUMN
+
+
+def sweep_source_digest() -> str:
+    """SHA-256 over the sources the sweep kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_14823_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(cfg_name, mode):
+    """HBM bytes per sweep launch measured by the FETCH_SIZE / WRITE_SIZE
+    counters (already scaled by the copy-kernel calibration), read from the
+    profile summary of this workload; None when there is none or when it was
+    taken on kernel sources other than the current ones."""
+    path = os.path.join(ROOT, "profiles", "sweep_kernel_%s_%s_hbm_counters.md" % (cfg_name, mode))
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^\s*-?\s*`?(source_sha256|hbm_bytes_per_launch)`?\s*[:=]\s*`?([0-9a-fA-F.eE+]+)`?", line)
+            if m:
+                rec[m.group(1)] = m.group(2)
+    if rec.get("source_sha256") != sweep_source_digest() or "hbm_bytes_per_launch" not in rec:
+        return None
+    return float(rec["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(st, dz, dt, budget_s=12.0):
@@ -163,6 +194,7 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     alg = algorithmic_bytes(cfg, mask)
     achieved = alg / (kern_ms * 1e-3) / 1e9
+    traffic = recorded_traffic(cfg.name, args.mode) if args.mode != "surrogate" else None
     line = {
         "metric": "grid-point updates/s: FP64 plain vs FP32-mixed vs MLP surrogate @ stated error",
         "value": points / (wall / args.steps),
@@ -182,7 +214,7 @@ def main():
                                   cfg.dt, cfg.seed),
                    "columns": cfg.ncol, "levels": cfg.nlev, "points": points, "mode": args.mode},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "sweep_kernel", "kernel_ms": kern_ms, "algorithmic_bytes": alg},
         "status": status,
     }
