@@ -27,13 +27,23 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                 "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+# Per-file additions.  The sweep kernels are one long loop whose body uses
+# many compile-time binary64 constants: hoisting their materialisation out of
+# the loop (machine LICM) or merging repeated ones (machine CSE) keeps them
+# live across the whole body, which overflows the scalar registers into
+# vector-lane spills and costs more vector instructions than it saves.
+FILE_FLAGS = {
+    "casim_sweep.hip": ["-mllvm", "-disable-machine-licm", "-mllvm", "-disable-machine-cse"],
+}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *DEVICE_FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *DEVICE_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))

@@ -20,6 +20,18 @@
 
 namespace casim {
 
+// a*b + c with c a compile-time constant: one v_fma_f64 taking c from a
+// scalar register pair.  Left to itself the compiler materialises such an
+// addend in the destination vector registers and uses the two-operand
+// v_fmac_f64 form, three vector instructions instead of one.  a and b must
+// not come straight from a transcendental instruction (v_rcp_f64 etc.): the
+// hazard recognizer does not look inside inline assembly.
+__device__ __forceinline__ double fma_sc(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
 __device__ __forceinline__ double exp64(double x) {
     const double log2e = 1.4426950408889634074;
     const double ln2_hi = 6.93147180369123816490e-01;   // upper bits of ln 2
@@ -28,17 +40,16 @@ __device__ __forceinline__ double exp64(double x) {
     double r = __builtin_fma(-kd, ln2_hi, x);
     r = __builtin_fma(-kd, ln2_lo, r);
     // Horner form of sum_{n=0}^{13} r^n / n!
-    double p = 1.0 / 6227020800.0;                       // 1/13!
-    p = __builtin_fma(p, r, 1.0 / 479001600.0);          // 1/12!
-    p = __builtin_fma(p, r, 1.0 / 39916800.0);
-    p = __builtin_fma(p, r, 1.0 / 3628800.0);
-    p = __builtin_fma(p, r, 1.0 / 362880.0);
-    p = __builtin_fma(p, r, 1.0 / 40320.0);
-    p = __builtin_fma(p, r, 1.0 / 5040.0);
-    p = __builtin_fma(p, r, 1.0 / 720.0);
-    p = __builtin_fma(p, r, 1.0 / 120.0);
-    p = __builtin_fma(p, r, 1.0 / 24.0);
-    p = __builtin_fma(p, r, 1.0 / 6.0);
+    double p = fma_sc(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);   // 1/13!, 1/12!
+    p = fma_sc(p, r, 1.0 / 39916800.0);
+    p = fma_sc(p, r, 1.0 / 3628800.0);
+    p = fma_sc(p, r, 1.0 / 362880.0);
+    p = fma_sc(p, r, 1.0 / 40320.0);
+    p = fma_sc(p, r, 1.0 / 5040.0);
+    p = fma_sc(p, r, 1.0 / 720.0);
+    p = fma_sc(p, r, 1.0 / 120.0);
+    p = fma_sc(p, r, 1.0 / 24.0);
+    p = fma_sc(p, r, 1.0 / 6.0);
     p = __builtin_fma(p, r, 0.5);
     p = __builtin_fma(p, r, 1.0);
     p = __builtin_fma(p, r, 1.0);
@@ -58,16 +69,15 @@ __device__ __forceinline__ double log64(double x) {
     const double s = (m - 1.0) * rm;
     const double z = s * s;
     // sum_{j=0}^{10} z^j / (2j+1)
-    double q = 1.0 / 21.0;
-    q = __builtin_fma(q, z, 1.0 / 19.0);
-    q = __builtin_fma(q, z, 1.0 / 17.0);
-    q = __builtin_fma(q, z, 1.0 / 15.0);
-    q = __builtin_fma(q, z, 1.0 / 13.0);
-    q = __builtin_fma(q, z, 1.0 / 11.0);
-    q = __builtin_fma(q, z, 1.0 / 9.0);
-    q = __builtin_fma(q, z, 1.0 / 7.0);
-    q = __builtin_fma(q, z, 1.0 / 5.0);
-    q = __builtin_fma(q, z, 1.0 / 3.0);
+    double q = fma_sc(z, 1.0 / 21.0, 1.0 / 19.0);
+    q = fma_sc(q, z, 1.0 / 17.0);
+    q = fma_sc(q, z, 1.0 / 15.0);
+    q = fma_sc(q, z, 1.0 / 13.0);
+    q = fma_sc(q, z, 1.0 / 11.0);
+    q = fma_sc(q, z, 1.0 / 9.0);
+    q = fma_sc(q, z, 1.0 / 7.0);
+    q = fma_sc(q, z, 1.0 / 5.0);
+    q = fma_sc(q, z, 1.0 / 3.0);
     q = __builtin_fma(q, z, 1.0);
     const double ed = (double)e;
     const double lm = 2.0 * s * q;

@@ -446,10 +446,17 @@ __device__ __forceinline__ void sediment(const DevParams &P, int cat, int ns, do
     }
 }
 
-template <bool MIX, bool FAST, int C, bool SUR>
+// Kernel variants: VAR_GENERIC takes the constants and the stage/warm
+// switches at run time; VAR_COLD and VAR_WARM have the default constants and
+// all four stages compiled in (cold or warm configuration), which keeps the
+// switches and constants out of the scalar registers.
+enum { VAR_GENERIC = 0, VAR_COLD = 1, VAR_WARM = 2 };
+
+template <bool MIX, int VAR, int C, bool SUR>
 __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) {
     using R = typename std::conditional<MIX, float, double>::type;
     constexpr int L = kWave / C;
+    constexpr bool FAST = VAR != VAR_GENERIC;
     const DevParams &P = params<FAST>(Prt);
     extern __shared__ double lds_all[];
     const int lane = threadIdx.x & (kWave - 1);
@@ -459,10 +466,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
     const int64_t col = ((int64_t)blockIdx.x * (blockDim.x / kWave) + wib) * C + c;
     const bool colvalid = col < a.ncol;
     const double dt = a.dt, inv_dt = 1.0 / dt;
-    const bool warm = a.warm != 0;
+    const bool warm = FAST ? VAR == VAR_WARM : a.warm != 0;
     const int ncat = warm ? 1 : 4;
-    const bool do_adj = a.stages & CASIM_STAGE_ADJUST, do_sat = a.stages & CASIM_STAGE_SATADJ;
-    const bool do_rates = a.stages & CASIM_STAGE_RATES, do_sed = a.stages & CASIM_STAGE_SED;
+    const bool do_adj = FAST || (a.stages & CASIM_STAGE_ADJUST), do_sat = FAST || (a.stages & CASIM_STAGE_SATADJ);
+    const bool do_rates = FAST || (a.stages & CASIM_STAGE_RATES), do_sed = FAST || (a.stages & CASIM_STAGE_SED);
 
     for (int j = lane; j < (a.nslots + 8) * C; j += kWave) lds[j] = 0.0;
     unsigned long long carry_cols = 0;   // bit c: a flux enters column c's next chunk from above
@@ -761,17 +768,25 @@ int env_int(const char *name, int dflt) {
     return e ? atoi(e) : dflt;
 }
 
-template <bool MIX, bool FAST, bool SUR>
+template <bool MIX, int VAR, bool SUR>
 hipError_t launch_c(int C, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &P,
                     const SweepArgs &a) {
     switch (C) {
-        case 4: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 4, SUR>), grid, block, lds, s, P, a); break;
-        case 8: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 8, SUR>), grid, block, lds, s, P, a); break;
-        case 16: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 16, SUR>), grid, block, lds, s, P, a); break;
-        case 32: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 32, SUR>), grid, block, lds, s, P, a); break;
-        default: hipLaunchKernelGGL((sweep_kernel<MIX, FAST, 64, SUR>), grid, block, lds, s, P, a); break;
+        case 4: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 4, SUR>), grid, block, lds, s, P, a); break;
+        case 8: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 8, SUR>), grid, block, lds, s, P, a); break;
+        case 16: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 16, SUR>), grid, block, lds, s, P, a); break;
+        case 32: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 32, SUR>), grid, block, lds, s, P, a); break;
+        default: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 64, SUR>), grid, block, lds, s, P, a); break;
     }
     return hipGetLastError();
+}
+
+template <bool MIX, bool SUR>
+hipError_t launch_var(int var, int C, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &P,
+                      const SweepArgs &a) {
+    if (var == VAR_COLD) return launch_c<MIX, VAR_COLD, SUR>(C, grid, block, lds, s, P, a);
+    if (var == VAR_WARM) return launch_c<MIX, VAR_WARM, SUR>(C, grid, block, lds, s, P, a);
+    return launch_c<MIX, VAR_GENERIC, SUR>(C, grid, block, lds, s, P, a);
 }
 
 }  // namespace
@@ -800,14 +815,11 @@ hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipSt
     const int64_t waves = (a.ncol + C - 1) / C;
     const int64_t blocks = (waves + wpb - 1) / wpb;
     const dim3 grid((unsigned)blocks), block(wpb * kWave);
-    if (a.mode == CASIM_MODE_FP32MIX)
-        return fast ? launch_c<true, true, false>(C, grid, block, lds, stream, P, a)
-                    : launch_c<true, false, false>(C, grid, block, lds, stream, P, a);
-    if (a.mode == CASIM_MODE_SURROGATE)
-        return fast ? launch_c<false, true, true>(C, grid, block, lds, stream, P, a)
-                    : launch_c<false, false, true>(C, grid, block, lds, stream, P, a);
-    return fast ? launch_c<false, true, false>(C, grid, block, lds, stream, P, a)
-                : launch_c<false, false, false>(C, grid, block, lds, stream, P, a);
+    // the compiled-in variants need the default constants and all stages
+    const int var = !(fast && a.stages == CASIM_STAGE_ALL) ? VAR_GENERIC : (a.warm ? VAR_WARM : VAR_COLD);
+    if (a.mode == CASIM_MODE_FP32MIX) return launch_var<true, false>(var, C, grid, block, lds, stream, P, a);
+    if (a.mode == CASIM_MODE_SURROGATE) return launch_var<false, true>(var, C, grid, block, lds, stream, P, a);
+    return launch_var<false, false>(var, C, grid, block, lds, stream, P, a);
 }
 
 hipError_t launch_points(const DevParams &P, bool fast, const PointArgs &pa, hipStream_t stream) {
