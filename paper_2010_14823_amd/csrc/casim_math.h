@@ -32,6 +32,14 @@ __device__ __forceinline__ double fma_sc(double a, double b, double c) {
     return d;
 }
 
+// c1*a + c0 with both constants from scalar registers (a multiply and an
+// add: one instruction cannot read two scalar pairs).
+__device__ __forceinline__ double lin_sc(double a, double c1, double c0) {
+    double d;
+    asm("v_mul_f64 %0, %1, %2\n\tv_add_f64 %0, %0, %3" : "=&v"(d) : "v"(a), "s"(c1), "s"(c0));
+    return d;
+}
+
 __device__ __forceinline__ double exp64(double x) {
     const double log2e = 1.4426950408889634074;
     const double ln2_hi = 6.93147180369123816490e-01;   // upper bits of ln 2
@@ -40,7 +48,7 @@ __device__ __forceinline__ double exp64(double x) {
     double r = __builtin_fma(-kd, ln2_hi, x);
     r = __builtin_fma(-kd, ln2_lo, r);
     // Horner form of sum_{n=0}^{13} r^n / n!
-    double p = fma_sc(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);   // 1/13!, 1/12!
+    double p = lin_sc(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);   // 1/13!, 1/12!
     p = fma_sc(p, r, 1.0 / 39916800.0);
     p = fma_sc(p, r, 1.0 / 3628800.0);
     p = fma_sc(p, r, 1.0 / 362880.0);
@@ -69,7 +77,7 @@ __device__ __forceinline__ double log64(double x) {
     const double s = (m - 1.0) * rm;
     const double z = s * s;
     // sum_{j=0}^{10} z^j / (2j+1)
-    double q = fma_sc(z, 1.0 / 21.0, 1.0 / 19.0);
+    double q = lin_sc(z, 1.0 / 21.0, 1.0 / 19.0);
     q = fma_sc(q, z, 1.0 / 17.0);
     q = fma_sc(q, z, 1.0 / 15.0);
     q = fma_sc(q, z, 1.0 / 13.0);
