@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c1")
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32mix", "surrogate"])
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32mix", "surrogate", "fp64compact"])
     ap.add_argument("--checkpoint", default=None, help="surrogate checkpoint (casim_mlp_save blob)")
     ap.add_argument("--compare", action="store_true",
                     help="also run one plain binary64 step and report the per-field error of this mode")
@@ -161,7 +161,8 @@ def main():
     dev = torch.from_numpy(st).cuda()
     tend = torch.empty((12, cfg.nlev, cfg.ncol), dtype=torch.float64, device="cuda")
     sfc = torch.empty((8, cfg.ncol), dtype=torch.float64, device="cuda")
-    mode = {"fp64": casim.MODE_FP64, "fp32mix": casim.MODE_FP32MIX, "surrogate": casim.MODE_SURROGATE}[args.mode]
+    mode = {"fp64": casim.MODE_FP64, "fp32mix": casim.MODE_FP32MIX, "surrogate": casim.MODE_SURROGATE,
+            "fp64compact": casim.MODE_FP64_COMPACT}[args.mode]
     if args.mode == "surrogate":
         if not args.checkpoint:
             print("--mode surrogate needs --checkpoint", file=sys.stderr)
@@ -206,7 +207,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.mode == "fp64" else "f32+f64",
+        "dtype": "f64" if args.mode in ("fp64", "fp64compact") else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "%s %s step: %d columns x %d levels, %s cloudy columns, dt=%g s, seed %d"
                                % (cfg.name, args.mode, cfg.ncol, cfg.nlev,
@@ -215,7 +216,9 @@ def main():
                    "columns": cfg.ncol, "levels": cfg.nlev, "points": points, "mode": args.mode},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "sweep_kernel", "kernel_ms": kern_ms, "algorithmic_bytes": alg},
+                     "kernel": "sweep_kernel" if args.mode in ("fp64", "fp32mix")
+                               else "whole step: point pass, rate kernel, sweep",
+                     "kernel_ms": kern_ms, "algorithmic_bytes": alg},
         "status": status,
     }
     print("bench: %.4f ms/step on the GPU" % ms_per_step, file=sys.stderr, flush=True)

@@ -52,6 +52,15 @@ extern "C" {
                                    binary32; saturation adjustment, fluxes,
                                    level updates and surface sums binary64 */
 #define CASIM_MODE_SURROGATE 2  /* process rates from the learned MLP      */
+#define CASIM_MODE_FP64_COMPACT 3  /* binary64 like CASIM_MODE_FP64, with the
+                                   12 rates evaluated by a separate kernel
+                                   over a dense list of the points whose
+                                   rate gates are open (ballot and prefix
+                                   compaction; the post-adjustment state
+                                   and the rates are staged through device
+                                   memory).  Same results as CASIM_MODE_FP64
+                                   to rounding; it trades HBM traffic for
+                                   full wavefronts in the rate evaluation. */
 
 #define CASIM_STAGE_ADJUST 1    /* clean-up + instant phase changes        */
 #define CASIM_STAGE_SATADJ 2    /* liquid saturation adjustment            */

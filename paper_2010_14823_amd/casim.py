@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcasim.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "casim.h")
 
-MODE_FP64, MODE_FP32MIX, MODE_SURROGATE = 0, 1, 2
+MODE_FP64, MODE_FP32MIX, MODE_SURROGATE, MODE_FP64_COMPACT = 0, 1, 2, 3
 STAGE_ADJUST, STAGE_SATADJ, STAGE_RATES, STAGE_SED, STAGE_ALL = 1, 2, 4, 8, 15
 FLAG_GENERIC = 1
 NIN, NTEND, NSFC = 14, 12, 8

@@ -27,13 +27,18 @@ struct Context {
     // rate-dump scratch: per-block counts and offsets, total
     int64_t *d_counts = nullptr, *d_offsets = nullptr, *d_total = nullptr;
     int64_t dump_blocks = 0;
-    // surrogate-step scratch, sized for sur_cap points
+    // slot of every point and the slot counter (surrogate and compacted steps)
     int32_t *d_idx = nullptr;
+    unsigned long long *d_count = nullptr;
+    int64_t idx_cap = 0;
+    // surrogate-step scratch, sized for sur_cap points
     float *d_feat = nullptr, *d_rates = nullptr;
     uint16_t *d_gates = nullptr;
     uint8_t *d_fb = nullptr;
-    unsigned long long *d_count = nullptr;
     int64_t sur_cap = 0;
+    // compacted-step scratch: post-adjustment state [13][cmp_cap], rates [12][cmp_cap]
+    double *d_cstate = nullptr, *d_crates = nullptr;
+    int64_t cmp_cap = 0;
 };
 
 Context g;
@@ -53,7 +58,7 @@ bool pos_finite(double x) { return isfinite(x) && x > 0.0; }
 
 int validate_constants(const casim_constants *c, const casim_thresholds *t) {
     if (!c || !t) return CASIM_EINVAL;
-    if (c->mode < CASIM_MODE_FP64 || c->mode > CASIM_MODE_SURROGATE) return CASIM_EINVAL;
+    if (c->mode < CASIM_MODE_FP64 || c->mode > CASIM_MODE_FP64_COMPACT) return CASIM_EINVAL;
     if (c->stages < 0 || c->stages > CASIM_STAGE_ALL) return CASIM_EINVAL;
     const double pos[] = {c->R_d, c->R_v, c->cp, c->L_v, c->L_s, c->T_0, c->rho_w, c->rho_i,
                           c->rho_s, c->rho_g, c->rho_0, c->K_a, c->Dv0, c->esl_a, c->esi_a,
@@ -141,21 +146,61 @@ int upload_dz(const double *dz, int32_t nlev) {
     return CASIM_OK;
 }
 
-// Grow the surrogate-step scratch to hold npts points (drains the device
-// before freeing buffers a step in flight may use).
+// Slots per region of the slot space for a step over npts points (the point
+// pass runs 256-point blocks; block b fills region b % kSlotRegions).
+int64_t region_cap(int64_t npts) {
+    const int64_t blocks = (npts + 255) / 256;
+    return (blocks + kSlotRegions - 1) / kSlotRegions * 256;
+}
+
+// The grow functions below drain the device before freeing buffers a step
+// in flight may use.  Slot indices are int32, so the slot space of a step
+// (kSlotRegions * region_cap(npts) >= npts) holds at most 2^31-1 slots.
+int ensure_idx(int64_t npts) {
+    if (kSlotRegions * region_cap(npts) > INT32_MAX) return CASIM_ECAPACITY;
+    if (!g.d_count) HIP_TRY(hipMalloc(&g.d_count, sizeof(unsigned long long) * kSlotRegions * kCounterStride));
+    if (npts <= g.idx_cap) return CASIM_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    hipFree(g.d_idx);
+    g.d_idx = nullptr;
+    g.idx_cap = 0;
+    HIP_TRY(hipMalloc(&g.d_idx, sizeof(int32_t) * npts));
+    g.idx_cap = npts;
+    return CASIM_OK;
+}
+
+// Surrogate-step scratch for the slot space of npts points.
 int ensure_sur(int64_t npts) {
+    int rc = ensure_idx(npts);
+    if (rc) return rc;
+    npts = kSlotRegions * region_cap(npts);
     if (npts <= g.sur_cap) return CASIM_OK;
     HIP_TRY(hipDeviceSynchronize());
-    hipFree(g.d_idx); hipFree(g.d_feat); hipFree(g.d_rates); hipFree(g.d_gates); hipFree(g.d_fb);
-    g.d_idx = nullptr; g.d_feat = nullptr; g.d_rates = nullptr; g.d_gates = nullptr; g.d_fb = nullptr;
+    hipFree(g.d_feat); hipFree(g.d_rates); hipFree(g.d_gates); hipFree(g.d_fb);
+    g.d_feat = nullptr; g.d_rates = nullptr; g.d_gates = nullptr; g.d_fb = nullptr;
     g.sur_cap = 0;
-    HIP_TRY(hipMalloc(&g.d_idx, sizeof(int32_t) * npts));
     HIP_TRY(hipMalloc(&g.d_feat, sizeof(float) * 12 * npts));
     HIP_TRY(hipMalloc(&g.d_rates, sizeof(float) * 12 * npts));
     HIP_TRY(hipMalloc(&g.d_gates, sizeof(uint16_t) * npts));
     HIP_TRY(hipMalloc(&g.d_fb, npts));
-    if (!g.d_count) HIP_TRY(hipMalloc(&g.d_count, sizeof(unsigned long long)));
     g.sur_cap = npts;
+    return CASIM_OK;
+}
+
+// Compacted-step scratch for the slot space of npts points (room for every
+// point to be slotted).
+int ensure_cmp(int64_t npts) {
+    int rc = ensure_idx(npts);
+    if (rc) return rc;
+    npts = kSlotRegions * region_cap(npts);
+    if (npts <= g.cmp_cap) return CASIM_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    hipFree(g.d_cstate); hipFree(g.d_crates);
+    g.d_cstate = nullptr; g.d_crates = nullptr;
+    g.cmp_cap = 0;
+    HIP_TRY(hipMalloc(&g.d_cstate, sizeof(double) * kCmpState * npts));
+    HIP_TRY(hipMalloc(&g.d_crates, sizeof(double) * 12 * npts));
+    g.cmp_cap = npts;
     return CASIM_OK;
 }
 
@@ -189,6 +234,8 @@ int fill_args(const casim_state *s, int64_t ncol, int32_t nlev, double dt, Sweep
     a.sur_rates = nullptr;
     a.sur_fallback = nullptr;
     a.sur_f_min = g.t.sur_f_min;
+    a.cmp_rates = nullptr;
+    a.cmp_ld = 0;
     return CASIM_OK;
 }
 
@@ -274,7 +321,7 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
         // features and gates of every point that can react -> network -> sweep
         const int64_t npts = (int64_t)nlev * ncol;
         if ((rc = ensure_sur(npts))) return rc;
-        HIP_TRY(launch_zero_u64(g.d_count, st));
+        HIP_TRY(launch_zero_u64(g.d_count, (int64_t)kSlotRegions * kCounterStride, st));
         PointArgs pa{};
         pa.s = a;
         pa.mode = POINT_SURR;
@@ -282,12 +329,33 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
         pa.gates = g.d_gates;
         pa.idx_map = g.d_idx;
         pa.counter = g.d_count;
+        pa.rcap = region_cap(npts);
         HIP_TRY(launch_points(g.P, g.fast, pa, st));
         HIP_TRY(launch_surrogate_infer(surrogate_dev((float)g.t.sur_range_margin, (float)g.t.sur_maha_max),
-                                       g.d_feat, g.d_gates, npts, g.d_count, g.d_rates, g.d_fb, st));
+                                       g.d_feat, g.d_gates, npts, g.d_count, pa.rcap, g.d_rates, g.d_fb, st));
         a.sur_idx = g.d_idx;
         a.sur_rates = g.d_rates;
         a.sur_fallback = g.d_fb;
+    } else if (g.c.mode == CASIM_MODE_FP64_COMPACT) {
+        // post-adjustment state of every point with an open rate gate -> dense
+        // binary64 rates -> sweep
+        const int64_t npts = (int64_t)nlev * ncol;
+        if ((rc = ensure_cmp(npts))) return rc;
+        HIP_TRY(launch_zero_u64(g.d_count, (int64_t)kSlotRegions * kCounterStride, st));
+        PointArgs pa{};
+        pa.s = a;
+        pa.s.cmp_ld = g.cmp_cap;
+        pa.mode = POINT_CSTATE;
+        pa.idx_map = g.d_idx;
+        pa.counter = g.d_count;
+        pa.rcap = region_cap(npts);
+        pa.cstate = g.d_cstate;
+        HIP_TRY(launch_points(g.P, g.fast, pa, st));
+        HIP_TRY(launch_dense_rates(g.P, g.fast, a.warm != 0, g.d_cstate, g.cmp_cap, g.d_count, pa.rcap, g.d_crates,
+                                   st));
+        a.sur_idx = g.d_idx;
+        a.cmp_rates = g.d_crates;
+        a.cmp_ld = g.cmp_cap;
     }
     HIP_TRY(launch_sweep(g.P, g.fast, a, st));
     return CASIM_OK;
@@ -367,9 +435,10 @@ int casim_finalize(void) {
     g.d_counts = g.d_offsets = g.d_total = nullptr;
     g.dump_blocks = 0;
     hipFree(g.d_idx); hipFree(g.d_feat); hipFree(g.d_rates); hipFree(g.d_gates); hipFree(g.d_fb); hipFree(g.d_count);
+    hipFree(g.d_cstate); hipFree(g.d_crates);
     g.d_idx = nullptr; g.d_feat = nullptr; g.d_rates = nullptr; g.d_gates = nullptr; g.d_fb = nullptr;
-    g.d_count = nullptr;
-    g.sur_cap = 0;
+    g.d_count = nullptr; g.d_cstate = nullptr; g.d_crates = nullptr;
+    g.idx_cap = g.sur_cap = g.cmp_cap = 0;
     g.h_dz.clear();
     g.init = false;
     g.device = -1;

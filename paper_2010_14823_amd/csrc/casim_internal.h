@@ -113,6 +113,9 @@ struct SweepArgs {
     const float *sur_rates;
     const uint8_t *sur_fallback;
     double sur_f_min;
+    // compacted binary64 mode: rates[j * cmp_ld + slot] from the dense rate kernel
+    const double *cmp_rates;
+    int64_t cmp_ld;
 };
 
 // Point-parallel passes over (k, column) in point order p = k*ncol + c.
@@ -126,10 +129,26 @@ struct PointArgs {
     const int64_t *block_offsets;
     float *feat, *rates;
     uint16_t *gates;
-    int32_t *idx_map;              // surrogate: slot per point
-    unsigned long long *counter;   // surrogate: slots used
+    int32_t *idx_map;              // surrogate / compacted: slot per point
+    unsigned long long *counter;   // surrogate / compacted: slot counters, see kSlotRegions
+    int64_t rcap;                  // slots per region
+    double *cstate;                // compacted: post-adjustment state [13][cmp_ld]
 };
-enum { POINT_COUNT = 0, POINT_DUMP = 1, POINT_SURR = 2 };
+
+// Slot space of the surrogate and compacted steps: point-pass block b takes
+// its slots from region b % kSlotRegions, whose counter sits alone on a
+// 128-byte line at counter[r * kCounterStride].  A single counter for the
+// whole grid serialises millions of wavefront atomics on one L2 line.
+// Region r holds slots [r * rcap, r * rcap + count_r), with rcap =
+// ceil(blocks / kSlotRegions) * 256, so no region can overflow.
+constexpr int kSlotRegions = 1024;
+constexpr int kCounterStride = 16;
+enum { POINT_COUNT = 0, POINT_DUMP = 1, POINT_SURR = 2, POINT_CSTATE = 3 };
+
+// Post-adjustment state of a compacted point, the inputs of the rate block:
+// T, p, rho, qv, qc, nc, qr, nr, qi, ni, qs, qg and the liquid saturation
+// pressure at T.
+constexpr int kCmpState = 13;
 
 // Launchers (casim_sweep.hip).  `fast` selects the kernels compiled with
 // kDefaultParams.  Return the launch's hipError_t.
@@ -137,7 +156,11 @@ hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipSt
 hipError_t launch_apply(const SweepArgs &a, double dt, hipStream_t stream);
 hipError_t launch_math(const double *x, int64_t n, double *e, double *l, hipStream_t stream);
 hipError_t launch_points(const DevParams &P, bool fast, const PointArgs &pa, hipStream_t stream);
-hipError_t launch_zero_u64(unsigned long long *p, hipStream_t stream);
+// Rates of the filled slots of every region of the compacted state into
+// rates[12][ld] (ld = kSlotRegions * rcap).
+hipError_t launch_dense_rates(const DevParams &P, bool fast, bool warm, const double *cstate, int64_t ld,
+                              const unsigned long long *counters, int64_t rcap, double *rates, hipStream_t stream);
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t stream);
 hipError_t launch_scan(const int64_t *counts, int64_t n, int64_t *offsets, int64_t *total, hipStream_t stream);
 
 }  // namespace casim

@@ -42,11 +42,11 @@ struct SurrogateDev {
 bool surrogate_ready();
 SurrogateDev surrogate_dev(float range_margin, float maha_max);
 
-// rates/fallback for samples [0, n); when n_dev is not null the count is read
-// from device memory (n is then the capacity).
+// Network rates of feature rows: with counters (the slot space of a
+// surrogate step) the filled slots of each region, else rows [0, n).
 hipError_t launch_surrogate_infer(const SurrogateDev &S, const float *feat, const uint16_t *gates, int64_t n,
-                                  const unsigned long long *n_dev, float *rates, uint8_t *fallback,
-                                  hipStream_t stream);
+                                  const unsigned long long *counters, int64_t rcap, float *rates,
+                                  uint8_t *fallback, hipStream_t stream);
 
 }  // namespace casim
 

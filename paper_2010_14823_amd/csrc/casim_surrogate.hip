@@ -88,20 +88,32 @@ __device__ __forceinline__ void init_acc(f32x4 (&acc)[4][8], const float *bias, 
     }
 }
 
+// Rows of region r: [r * rcap, r * rcap + count), the count from the slot
+// counters of a step, else the part of [0, n_all) the region covers.
+__device__ __forceinline__ int64_t region_rows(const unsigned long long *counters, int64_t rcap, int64_t n_all,
+                                               int64_t r) {
+    if (counters) {
+        const unsigned long long c = counters[r * kCounterStride];
+        return (int64_t)(c < (unsigned long long)rcap ? c : (unsigned long long)rcap);
+    }
+    const int64_t cnt = n_all - r * rcap;
+    return cnt < 0 ? 0 : (cnt > rcap ? rcap : cnt);
+}
+
 __global__ __launch_bounds__(256) void surrogate_infer_kernel(const uint16_t *__restrict__ wglob,
                                                               const float *__restrict__ bias,
                                                               const float *__restrict__ stats_raw,
                                                               float range_margin, float maha_max_arg,
                                                               const float *__restrict__ feat,
-                                                              const uint16_t *__restrict__ gates, int64_t n_cap,
-                                                              const unsigned long long *__restrict__ n_dev,
+                                                              const uint16_t *__restrict__ gates, int64_t n_all,
+                                                              const unsigned long long *__restrict__ counters,
+                                                              int64_t rcap, int64_t nreg,
                                                               float *__restrict__ rates, uint8_t *__restrict__ fallback) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     __bf16 *W = reinterpret_cast<__bf16 *>(lds_raw);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __bf16 *act = W + kWElems + wv * kActElems;
     const casim_mlp_stats *S = reinterpret_cast<const casim_mlp_stats *>(stats_raw);
-    const int64_t n = n_dev ? (int64_t)(*n_dev < (unsigned long long)n_cap ? *n_dev : (unsigned long long)n_cap) : n_cap;
 
     // weights -> LDS, 16 bytes per load
     {
@@ -112,10 +124,11 @@ __global__ __launch_bounds__(256) void surrogate_infer_kernel(const uint16_t *__
     __syncthreads();
     const float maha_max = maha_max_arg > 0.0f ? maha_max_arg : S->maha_q999;
 
-    for (int64_t base = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * 64; base < n;
-         base += (int64_t)gridDim.x * kWavesPerBlock * 64) {
-        const int64_t p = base + lane;
-        const bool valid = p < n;
+    for (int64_t r = blockIdx.x; r < nreg; r += gridDim.x)
+    for (int64_t t = (int64_t)wv * 64, cnt = region_rows(counters, rcap, n_all, r); t < cnt;
+         t += kWavesPerBlock * 64) {
+        const int64_t p = r * rcap + t + lane;
+        const bool valid = t + lane < cnt;
         // ---- inputs: standardise, range check, Mahalanobis distance --------
         float z[12];
         bool out_of_range = false;
@@ -207,18 +220,23 @@ SurrogateDev surrogate_dev(float range_margin, float maha_max) {
 }
 
 hipError_t launch_surrogate_infer(const SurrogateDev &S, const float *feat, const uint16_t *gates, int64_t n,
-                                  const unsigned long long *n_dev, float *rates, uint8_t *fallback,
-                                  hipStream_t stream) {
+                                  const unsigned long long *counters, int64_t rcap, float *rates,
+                                  uint8_t *fallback, hipStream_t stream) {
     if (!SC.attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)surrogate_infer_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInferLds);
         if (e != hipSuccess) return e;
         SC.attr_set = true;
     }
-    const int64_t tiles = (n + kWavesPerBlock * 64 - 1) / (kWavesPerBlock * 64);
-    const int64_t blocks = tiles < 1024 ? (tiles < 1 ? 1 : tiles) : 1024;
+    int64_t nreg = kSlotRegions;
+    if (!counters) {       // plain rows: 1024 equal regions of whole 64-row tiles
+        rcap = ((n + kSlotRegions - 1) / kSlotRegions + 63) / 64 * 64;
+        nreg = (n + rcap - 1) / rcap;
+    }
+    const int64_t blocks = nreg < 1 ? 1 : nreg;
     hipLaunchKernelGGL(surrogate_infer_kernel, dim3((unsigned)blocks), dim3(kWavesPerBlock * 64), kInferLds, stream,
-                       S.w, S.bias, S.stats, S.range_margin, S.maha_max, feat, gates, n, n_dev, rates, fallback);
+                       S.w, S.bias, S.stats, S.range_margin, S.maha_max, feat, gates, n, counters, rcap, nreg, rates,
+                       fallback);
     return hipGetLastError();
 }
 
@@ -282,7 +300,7 @@ int casim_surrogate_infer(const float *feat, const uint16_t *gates, int64_t n, f
     const casim_thresholds *cur = casim_current_thresholds();
     if (cur) t = *cur;
     hipError_t e = launch_surrogate_infer(surrogate_dev((float)t.sur_range_margin, (float)t.sur_maha_max), feat,
-                                          gates, n, nullptr, rates, fallback, (hipStream_t)stream);
+                                          gates, n, nullptr, 0, rates, fallback, (hipStream_t)stream);
     if (e != hipSuccess) return casim_record_hip_error((int)e, hipGetErrorString(e));
     return CASIM_OK;
 }

@@ -452,7 +452,12 @@ __device__ __forceinline__ void sediment(const DevParams &P, int cat, int ns, do
 // switches and constants out of the scalar registers.
 enum { VAR_GENERIC = 0, VAR_COLD = 1, VAR_WARM = 2 };
 
-template <bool MIX, int VAR, int C, bool SUR>
+// Where the 12 rates of an active point come from: evaluated in the sweep
+// (SRC_PLAIN), the surrogate network's output for the point's slot
+// (SRC_NET), or the dense rate kernel's output for its slot (SRC_DENSE).
+enum { SRC_PLAIN = 0, SRC_NET = 1, SRC_DENSE = 2 };
+
+template <bool MIX, int VAR, int C, int SRC>
 __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) {
     using R = typename std::conditional<MIX, float, double>::type;
     constexpr int L = kWave / C;
@@ -560,8 +565,19 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
             if (do_rates) {
                 // without the adjustment stage the clean-up may still have moved T
                 if (!do_sat && w.T != T_in) es_now = esat_liq(P, w.T);
-                bool plain = true;
-                if constexpr (SUR) {
+                bool plain = SRC == SRC_PLAIN;
+                if constexpr (SRC == SRC_DENSE) {
+                    // no slot: every rate gate is closed and all 12 rates are zero
+                    const int slot = a.sur_idx[(int64_t)k * a.ncol + col];
+                    if (slot >= 0) {
+                        double rr[12];
+#pragma unroll
+                        for (int j = 0; j < 12; ++j) rr[j] = a.cmp_rates[(int64_t)j * a.cmp_ld + slot];
+                        apply_rates<double>(P, w, d, rr, dt);
+                    }
+                }
+                if constexpr (SRC == SRC_NET) {
+                    plain = true;
                     // network rates for this point, unless it falls back
                     const int slot = a.sur_idx[(int64_t)k * a.ncol + col];
                     if (slot >= 0) {
@@ -658,23 +674,25 @@ __global__ __launch_bounds__(256) void point_kernel(DevParams Prt, PointArgs pa)
         if (!act && do_sat) act = w.qv > q_of_e(P, es_l, p);
         if (!act && do_adj && !warm && w.T < P.T_nuc) act = w.qv > q_of_e(P, esat_ice(P, w.T), p);
     }
+    // slotted passes take every active point; the rate dump draws a sample
+    const bool slotted = pa.mode == POINT_SURR || pa.mode == POINT_CSTATE;
     bool sel = act;
-    if (pa.mode != POINT_SURR) sel = act && hash_uniform(pa.seed, (uint64_t)pid) < pa.keep;
+    if (!slotted) sel = act && hash_uniform(pa.seed, (uint64_t)pid) < pa.keep;
     unsigned g = 0;
     float f[12];
     double r[12];
+    double es_now = es_l;
     if (sel) {
         rho = a.in[2][ix];
         w.nc = a.in[5][ix]; w.nr = a.in[7][ix]; w.ni = a.in[9][ix];
         w.ns = a.in[11][ix]; w.ng = a.in[13][ix];
         const double T_in = w.T;
         if (do_adj) adjust(P, warm, w, d, p, rho);
-        double es_now = es_l;
         if (do_sat) satadj(P, a.newton_iters, w, d, p, T_in, es_l, es_now);
         if (!do_sat && w.T != T_in) es_now = esat_liq(P, w.T);
         g = gate_bits(P, warm, w, p, es_now);
-        if (pa.mode == POINT_SURR) sel = (g & 0xFFFu) != 0;
-        if (sel) {
+        if (slotted) sel = (g & 0xFFFu) != 0;
+        if (sel && pa.mode != POINT_CSTATE) {
             features(w, p, rho, f);
             if (pa.mode == POINT_DUMP)
                 rates<double>(P, warm, w, p, rho, log64(rho), ::sqrt(P.rho_0 / rho), es_now, r);
@@ -684,16 +702,27 @@ __global__ __launch_bounds__(256) void point_kernel(DevParams Prt, PointArgs pa)
     const unsigned long long bal = __ballot((int)sel);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int in_wave = __popcll(bal & ((1ull << lane) - 1ull));
-    if (pa.mode == POINT_SURR) {
+    if (slotted) {
+        // one atomic per wavefront reserves the wave's slots; a point's slot is
+        // the wave's base plus its rank among the selected lanes (mbcnt)
+        const int64_t region = blockIdx.x % kSlotRegions;
         unsigned long long base = 0;
-        if (lane == 0 && bal) base = atomicAdd(pa.counter, (unsigned long long)__popcll(bal));
+        if (lane == 0 && bal)
+            base = atomicAdd(pa.counter + region * kCounterStride, (unsigned long long)__popcll(bal));
         base = __shfl(base, 0);
-        if (valid) pa.idx_map[pid] = sel ? (int32_t)(base + in_wave) : -1;
+        const int64_t slot = region * pa.rcap + (int64_t)(base + in_wave);
+        if (valid) pa.idx_map[pid] = sel ? (int32_t)slot : -1;
         if (sel) {
-            const int64_t slot = (int64_t)(base + in_wave);
+            if (pa.mode == POINT_SURR) {
 #pragma unroll
-            for (int j = 0; j < 12; ++j) pa.feat[slot * 12 + j] = f[j];
-            pa.gates[slot] = (uint16_t)g;
+                for (int j = 0; j < 12; ++j) pa.feat[slot * 12 + j] = f[j];
+                pa.gates[slot] = (uint16_t)g;
+            } else {
+                const double v[kCmpState] = {w.T, p, rho, w.qv, w.qc, w.nc, w.qr, w.nr,
+                                             w.qi, w.ni, w.qs, w.qg, es_now};
+#pragma unroll
+                for (int j = 0; j < kCmpState; ++j) pa.cstate[(int64_t)j * a.cmp_ld + slot] = v[j];
+            }
         }
         return;
     }
@@ -718,10 +747,56 @@ __global__ __launch_bounds__(256) void point_kernel(DevParams Prt, PointArgs pa)
     }
 }
 
-__global__ void zero_u64_kernel(unsigned long long *p) { *p = 0ull; }
+// The 12 binary64 rates of compacted points, one point per lane with every
+// lane of a wavefront busy (grid-stride over the slots the point pass filled).
+// ln rho and (rho_0/rho)^1/2 are formed exactly as in the sweep.
+template <bool FAST>
+__global__ __launch_bounds__(256) void dense_rates_kernel(DevParams Prt, const double *cs, int64_t ld,
+                                                          const unsigned long long *counters, int64_t rcap,
+                                                          double *out, int warm_i) {
+    const DevParams &P = params<FAST>(Prt);
+    const bool warm = warm_i != 0;
+    // block r works through region r (one block per region)
+    const int64_t r = blockIdx.x;
+    const unsigned long long c = counters[r * kCounterStride];
+    const int64_t n = (int64_t)(c < (unsigned long long)rcap ? c : (unsigned long long)rcap);
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += blockDim.x) {
+        const int64_t i = r * rcap + i0;
+        Pt w{};
+        w.T = cs[i];
+        const double p = cs[ld + i], rho = cs[2 * ld + i];
+        w.qv = cs[3 * ld + i]; w.qc = cs[4 * ld + i]; w.nc = cs[5 * ld + i];
+        w.qr = cs[6 * ld + i]; w.nr = cs[7 * ld + i]; w.qi = cs[8 * ld + i];
+        w.ni = cs[9 * ld + i]; w.qs = cs[10 * ld + i]; w.qg = cs[11 * ld + i];
+        const double es = cs[12 * ld + i];
+        double r[12];
+        rates<double>(P, warm, w, p, rho, log64(rho), ::sqrt(P.rho_0 * rcp64(rho)), es, r);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) out[(int64_t)j * ld + i] = r[j];
+    }
+}
 
-hipError_t launch_zero_u64(unsigned long long *p, hipStream_t stream) {
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, stream, p);
+hipError_t launch_dense_rates(const DevParams &P, bool fast, bool warm, const double *cstate, int64_t ld,
+                              const unsigned long long *counters, int64_t rcap, double *rates, hipStream_t stream) {
+    if (ld < (int64_t)kSlotRegions * rcap) return hipErrorInvalidValue;
+    const dim3 grid(kSlotRegions), block(256);
+    if (fast)
+        hipLaunchKernelGGL(dense_rates_kernel<true>, grid, block, 0, stream, P, cstate, ld, counters, rcap, rates,
+                           warm ? 1 : 0);
+    else
+        hipLaunchKernelGGL(dense_rates_kernel<false>, grid, block, 0, stream, P, cstate, ld, counters, rcap, rates,
+                           warm ? 1 : 0);
+    return hipGetLastError();
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t stream) {
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, stream, p, n);
     return hipGetLastError();
 }
 
@@ -768,25 +843,25 @@ int env_int(const char *name, int dflt) {
     return e ? atoi(e) : dflt;
 }
 
-template <bool MIX, int VAR, bool SUR>
+template <bool MIX, int VAR, int SRC>
 hipError_t launch_c(int C, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &P,
                     const SweepArgs &a) {
     switch (C) {
-        case 4: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 4, SUR>), grid, block, lds, s, P, a); break;
-        case 8: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 8, SUR>), grid, block, lds, s, P, a); break;
-        case 16: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 16, SUR>), grid, block, lds, s, P, a); break;
-        case 32: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 32, SUR>), grid, block, lds, s, P, a); break;
-        default: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 64, SUR>), grid, block, lds, s, P, a); break;
+        case 4: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 4, SRC>), grid, block, lds, s, P, a); break;
+        case 8: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 8, SRC>), grid, block, lds, s, P, a); break;
+        case 16: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 16, SRC>), grid, block, lds, s, P, a); break;
+        case 32: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 32, SRC>), grid, block, lds, s, P, a); break;
+        default: hipLaunchKernelGGL((sweep_kernel<MIX, VAR, 64, SRC>), grid, block, lds, s, P, a); break;
     }
     return hipGetLastError();
 }
 
-template <bool MIX, bool SUR>
+template <bool MIX, int SRC>
 hipError_t launch_var(int var, int C, dim3 grid, dim3 block, size_t lds, hipStream_t s, const DevParams &P,
                       const SweepArgs &a) {
-    if (var == VAR_COLD) return launch_c<MIX, VAR_COLD, SUR>(C, grid, block, lds, s, P, a);
-    if (var == VAR_WARM) return launch_c<MIX, VAR_WARM, SUR>(C, grid, block, lds, s, P, a);
-    return launch_c<MIX, VAR_GENERIC, SUR>(C, grid, block, lds, s, P, a);
+    if (var == VAR_COLD) return launch_c<MIX, VAR_COLD, SRC>(C, grid, block, lds, s, P, a);
+    if (var == VAR_WARM) return launch_c<MIX, VAR_WARM, SRC>(C, grid, block, lds, s, P, a);
+    return launch_c<MIX, VAR_GENERIC, SRC>(C, grid, block, lds, s, P, a);
 }
 
 }  // namespace
@@ -817,9 +892,11 @@ hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipSt
     const dim3 grid((unsigned)blocks), block(wpb * kWave);
     // the compiled-in variants need the default constants and all stages
     const int var = !(fast && a.stages == CASIM_STAGE_ALL) ? VAR_GENERIC : (a.warm ? VAR_WARM : VAR_COLD);
-    if (a.mode == CASIM_MODE_FP32MIX) return launch_var<true, false>(var, C, grid, block, lds, stream, P, a);
-    if (a.mode == CASIM_MODE_SURROGATE) return launch_var<false, true>(var, C, grid, block, lds, stream, P, a);
-    return launch_var<false, false>(var, C, grid, block, lds, stream, P, a);
+    if (a.mode == CASIM_MODE_FP32MIX) return launch_var<true, SRC_PLAIN>(var, C, grid, block, lds, stream, P, a);
+    if (a.mode == CASIM_MODE_SURROGATE) return launch_var<false, SRC_NET>(var, C, grid, block, lds, stream, P, a);
+    if (a.mode == CASIM_MODE_FP64_COMPACT)
+        return launch_var<false, SRC_DENSE>(var, C, grid, block, lds, stream, P, a);
+    return launch_var<false, SRC_PLAIN>(var, C, grid, block, lds, stream, P, a);
 }
 
 hipError_t launch_points(const DevParams &P, bool fast, const PointArgs &pa, hipStream_t stream) {
