@@ -29,15 +29,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 KERNEL_SOURCES = ["casim_sweep.hip", "casim_internal.h", "casim_math.h", "casim_defaults.h"]
 B_CLOUDY, B_CLEAR, B_COLUMN = 208, 160, 64   # algorithmic bytes per point / column
+B_CLOUDY_WARM, B_CLEAR_WARM = 160, 136       # warm configuration: no ice-phase inputs
 
 
-def algorithmic_bytes(cfg, mask) -> int:
+def algorithmic_bytes(cfg, mask, warm=False) -> int:
     """Bytes a step must move: 14 reads + 12 writes (FP64) per point of a
     cloudy column, 8 reads + 12 writes per point of a clear column, 8 surface
-    writes per column."""
+    writes per column.  The warm configuration reads 8 and 5 fields (no ice,
+    snow or graupel) and still writes all 12 tendencies."""
     ncloudy = int(mask.sum())
     nclear = cfg.ncol - ncloudy
-    return cfg.nlev * (ncloudy * B_CLOUDY + nclear * B_CLEAR) + cfg.ncol * B_COLUMN
+    bc, bl = (B_CLOUDY_WARM, B_CLEAR_WARM) if warm else (B_CLOUDY, B_CLEAR)
+    return cfg.nlev * (ncloudy * bc + nclear * bl) + cfg.ncol * B_COLUMN
 
 
 def sweep_source_digest() -> str:
@@ -90,12 +93,12 @@ def cpu_baseline(st, dz, dt, budget_s=12.0):
                       % (st.shape[2], st.shape[1], len(times), t)}
 
 
-def compare_with_plain(torch, casim, dev, dz, cfg, tend, sfc, mode):
+def compare_with_plain(torch, casim, dev, dz, cfg, tend, sfc, mode, warm=0):
     """Per-field error of one step of `mode` against one plain binary64 step on
     the same state, both on the GPU: normwise max|d|/max|plain| and RMS."""
     casim.step(dev, dz, cfg.dt, tend, sfc)
     t_mode, s_mode = tend.clone(), sfc.clone()
-    casim.init(casim.default_constants(mode=casim.MODE_FP64))
+    casim.init(casim.default_constants(mode=casim.MODE_FP64, warm=warm))
     casim.step(dev, dz, cfg.dt, tend, sfc)
     torch.cuda.synchronize()
     out = {}
@@ -107,7 +110,7 @@ def compare_with_plain(torch, casim, dev, dz, cfg, tend, sfc, mode):
         out[name] = {"max_rel": (d.max().item() / den) if den > 0 else (0.0 if d.max().item() == 0 else None),
                      "rms_rel": ((d.pow(2).mean().sqrt().item() / b.pow(2).mean().sqrt().item())
                                  if den > 0 else None)}
-    casim.init(casim.default_constants(mode=mode))
+    casim.init(casim.default_constants(mode=mode, warm=warm))
     return out
 
 
@@ -128,6 +131,47 @@ def copy_probe(torch, nbytes=2 << 30, reps=5):
     return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms, "GBps": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def host_pipeline(torch, casim, st, dz, dt, nblocks=0, reps=3):
+    """casim_step_host on page-locked host copies of the workload: time per
+    step including both PCIe directions, and the same step overlapped with a
+    host workload (the parent model's other components) of similar length."""
+    nf, nlev, ncol = st.shape
+    hin, hout, hsfc = casim.HostArray(st.shape), casim.HostArray((12, nlev, ncol)), casim.HostArray((8, ncol))
+    hin.array[:] = st
+    casim.step_host(hin.array, dz, dt, hout.array, hsfc.array, nblocks=nblocks)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        casim.step_host(hin.array, dz, dt, hout.array, hsfc.array, nblocks=nblocks)
+        torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / reps
+    # a host workload of about the same length: dense products on the CPU
+    a = np.random.default_rng(0).standard_normal((600, 600))
+    n_mm = 1
+    while True:
+        t0 = time.perf_counter()
+        for _ in range(n_mm):
+            a = np.tanh(a @ a * 1e-3)
+        t_host = time.perf_counter() - t0
+        if t_host >= t_step or n_mm > 4096:
+            break
+        n_mm *= 2
+    t0 = time.perf_counter()
+    casim.step_host(hin.array, dz, dt, hout.array, hsfc.array, nblocks=nblocks)
+    for _ in range(n_mm):
+        a = np.tanh(a @ a * 1e-3)
+    torch.cuda.synchronize()
+    t_both = time.perf_counter() - t0
+    h2d = st.nbytes
+    d2h = 12 * nlev * ncol * 8 + 8 * ncol * 8
+    for h in (hin, hout, hsfc):
+        h.free()
+    return {"ms_per_step": t_step * 1e3, "points_per_s": nlev * ncol / t_step, "nblocks": nblocks or 4,
+            "bytes_h2d": h2d, "bytes_d2h": d2h, "pcie_GBps_both_directions": (h2d + d2h) / t_step / 1e9,
+            "overlap": {"host_work_ms": t_host * 1e3, "step_ms": t_step * 1e3,
+                        "concurrent_ms": t_both * 1e3, "serial_ms": (t_host + t_step) * 1e3}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +183,11 @@ def main():
     ap.add_argument("--compare", action="store_true",
                     help="also run one plain binary64 step and report the per-field error of this mode")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--warm", action="store_true",
+                    help="warm configuration (ice, snow and graupel processes off and not read)")
+    ap.add_argument("--host-pipeline", action="store_true",
+                    help="also time casim_step_host (state in page-locked host memory, both PCIe "
+                         "directions included) alone and overlapped with a host workload")
     ap.add_argument("--with-copy", action="store_true",
                     help="also time a plain device-to-device copy of 2 GiB (bandwidth reference "
                          "and scale for the HBM byte counters)")
@@ -170,7 +219,7 @@ def main():
         casim.init()
         casim.mlp_load(open(args.checkpoint, "rb").read())
         casim.surrogate_load()
-    casim.init(casim.default_constants(mode=mode))
+    casim.init(casim.default_constants(mode=mode, warm=1 if args.warm else 0))
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -193,9 +242,9 @@ def main():
 
     points = cfg.ncol * cfg.nlev
     ms_per_step = wall * 1e3 / args.steps
-    alg = algorithmic_bytes(cfg, mask)
+    alg = algorithmic_bytes(cfg, mask, args.warm)
     achieved = alg / (kern_ms * 1e-3) / 1e9
-    traffic = recorded_traffic(cfg.name, args.mode) if args.mode != "surrogate" else None
+    traffic = recorded_traffic(cfg.name, args.mode) if args.mode in ("fp64", "fp32mix") and not args.warm else None
     line = {
         "metric": "grid-point updates/s: FP64 plain vs FP32-mixed vs MLP surrogate @ stated error",
         "value": points / (wall / args.steps),
@@ -209,11 +258,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.mode in ("fp64", "fp64compact") else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "%s %s step: %d columns x %d levels, %s cloudy columns, dt=%g s, seed %d"
-                               % (cfg.name, args.mode, cfg.ncol, cfg.nlev,
+        "config": {"workload": "%s %s%s step: %d columns x %d levels, %s cloudy columns, dt=%g s, seed %d"
+                               % (cfg.name, args.mode, " warm" if args.warm else "", cfg.ncol, cfg.nlev,
                                   "all" if cfg.cloud_frac is None else "%d%%" % round(100 * cfg.cloud_frac),
                                   cfg.dt, cfg.seed),
-                   "columns": cfg.ncol, "levels": cfg.nlev, "points": points, "mode": args.mode},
+                   "columns": cfg.ncol, "levels": cfg.nlev, "points": points, "mode": args.mode,
+                   "configuration": "warm" if args.warm else "cold"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "sweep_kernel" if args.mode in ("fp64", "fp32mix")
@@ -226,9 +276,12 @@ def main():
         line["surrogate"] = {"fallback_points_per_step": status["fallback"] / args.steps,
                              "inferred_points_per_step": status["inferred"] / args.steps}
     if args.compare and args.mode != "fp64":
-        line["error_vs_fp64_plain"] = compare_with_plain(torch, casim, dev, dz, cfg, tend, sfc, mode)
+        line["error_vs_fp64_plain"] = compare_with_plain(torch, casim, dev, dz, cfg, tend, sfc, mode,
+                                                           1 if args.warm else 0)
     if args.with_copy:
         line["copy_probe"] = copy_probe(torch)
+    if args.host_pipeline:
+        line["host_pipeline"] = host_pipeline(torch, casim, st, dz, cfg.dt)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(st, dz, cfg.dt)
     print(json.dumps(line), flush=True)

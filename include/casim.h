@@ -300,6 +300,44 @@ int casim_surrogate_load(void);
 int casim_surrogate_infer(const float *feat, const uint16_t *gates, int64_t n, float *rates,
                           uint8_t *fallback, void *stream);
 
+/* ======================================================================
+ * Host-resident state: copy in, step, copy out.
+ *
+ * The deployment of the scheme inside a parent model (Sec. II-A and III-B of
+ * the CASIM port study): once per step the inputs are copied to the device
+ * asynchronously, the parent model keeps computing its other components on
+ * the CPU while the step runs, and then waits for the source terms, which
+ * are copied back.  casim_step_host does this for a state held in host
+ * memory.  The domain is cut into nblocks column blocks (0: 4); for each
+ * block it enqueues the copy of the 14 input fields into library-owned
+ * device buffers, the step on that block and the copy of its 12 tendencies
+ * and 8 surface values back, on three internal streams with two buffer
+ * sets, so that block b's step overlaps block b+1's inbound and block b-1's
+ * outbound copies.  `stream` first orders the internal streams after its
+ * own prior work and finally waits for the last outbound copy.  The call
+ * returns after enqueueing; outputs are valid once `stream` has been
+ * synchronised, and the inputs must not change before that.  Copies are
+ * asynchronous only from page-locked memory (casim_host_alloc).
+ *
+ * Arguments and errors as casim_step; every pointer of casim_host_state is a
+ * HOST pointer with the layout of casim_state.  The device buffers grow to
+ * the largest block seen and are freed by casim_finalize. */
+typedef struct casim_host_state {
+    const double *in[CASIM_NIN];
+    const double *dz;
+    int64_t ld;
+    double *tend[CASIM_NTEND];
+    double *sfc[CASIM_NSFC];
+} casim_host_state;
+
+int casim_step_host(const casim_host_state *hs, int64_t ncol, int32_t nlev, double dt, int32_t nblocks,
+                    void *stream);
+
+/* Page-locked host memory for casim_step_host (hipHostMalloc); *p is NULL on
+ * failure.  Errors: EINVAL (NULL p), EHIP. */
+int casim_host_alloc(void **p, size_t bytes);
+int casim_host_free(void *p);
+
 /* Diagnostics: evaluate the binary64 exponential and logarithm that the
  * step kernels use internally, elementwise on n device values x (x > 0 for a
  * meaningful log), into device arrays exp_out and log_out (either may be

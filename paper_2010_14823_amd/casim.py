@@ -54,6 +54,12 @@ class State(ctypes.Structure):
                 ("sfc", ctypes.c_void_p * NSFC)]
 
 
+class HostState(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p * NIN), ("dz", ctypes.POINTER(ctypes.c_double)),
+                ("ld", ctypes.c_int64), ("tend", ctypes.c_void_p * NTEND),
+                ("sfc", ctypes.c_void_p * NSFC)]
+
+
 class StepStatus(ctypes.Structure):
     _fields_ = [("newton_fail", ctypes.c_int64), ("nonfinite", ctypes.c_int64),
                 ("fallback", ctypes.c_int64), ("inferred", ctypes.c_int64)]
@@ -99,6 +105,9 @@ def lib():
             "casim_default_thresholds": [ctypes.POINTER(Thresholds)],
             "casim_init": [ctypes.POINTER(Constants), ctypes.POINTER(Thresholds)],
             "casim_step": [ctypes.POINTER(State), i64, i32, dbl, vp],
+            "casim_step_host": [ctypes.POINTER(HostState), i64, i32, dbl, i32, vp],
+            "casim_host_alloc": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t],
+            "casim_host_free": [vp],
             "casim_apply_tendencies": [ctypes.POINTER(State), i64, i32, dbl, vp],
             "casim_status": [vp, ctypes.POINTER(StepStatus)],
             "casim_finalize": [],
@@ -349,3 +358,58 @@ def surrogate_load():
 def surrogate_infer(feat, gates, n, rates, fallback, stream=None):
     _check(lib().casim_surrogate_infer(_p(feat), _p(gates), int(n), _p(rates), _p(fallback),
                                        _stream_handle(stream)), "casim_surrogate_infer")
+
+
+class HostArray:
+    """Page-locked host memory from casim_host_alloc, viewed as a float64 numpy
+    array of the given shape; freed with ``free()`` (or when collected)."""
+
+    def __init__(self, shape):
+        import numpy as np
+        self.shape = tuple(int(x) for x in shape)
+        n = int(np.prod(self.shape))
+        self._p = ctypes.c_void_p()
+        _check(lib().casim_host_alloc(ctypes.byref(self._p), max(n, 1) * 8), "casim_host_alloc")
+        buf = (ctypes.c_double * max(n, 1)).from_address(self._p.value)
+        self.array = np.frombuffer(buf, dtype=np.float64, count=n).reshape(self.shape)
+
+    def free(self):
+        if self._p is not None and self._p.value:
+            self.array = None
+            _check(lib().casim_host_free(self._p), "casim_host_free")
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def step_host(state, dz, dt: float, tend, sfc, ncol: int | None = None, nblocks: int = 0, stream=None):
+    """Enqueue casim_step_host on host arrays: state (14, nlev, ld), tend
+    (12, nlev, ld), sfc (8, >= ncol), float64 C-contiguous numpy arrays
+    (page-locked, e.g. HostArray, for the copies to be asynchronous).  The
+    outputs are valid after the stream is synchronised."""
+    import numpy as np
+    for name, a, lead in (("state", state, NIN), ("tend", tend, NTEND), ("sfc", sfc, NSFC)):
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous):
+            raise ValueError("%s must be a C-contiguous float64 numpy array" % name)
+        if a.shape[0] != lead:
+            raise ValueError("%s must have %d fields" % (name, lead))
+    nlev, ld = state.shape[1], state.shape[2]
+    ncol = ld if ncol is None else int(ncol)
+    if tend.shape[1:] != state.shape[1:] or sfc.shape[-1] < ncol:
+        raise ValueError("tend must match state's (nlev, ld) and sfc hold ncol columns")
+    hs = HostState()
+    for f in range(NIN):
+        hs.in_[f] = state[f].ctypes.data
+    for f in range(NTEND):
+        hs.tend[f] = tend[f].ctypes.data
+    for f in range(NSFC):
+        hs.sfc[f] = sfc[f].ctypes.data
+    dzh = np.ascontiguousarray(dz, dtype=np.float64)
+    hs.dz = dzh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    hs.ld = ld
+    _check(lib().casim_step_host(ctypes.byref(hs), ncol, nlev, float(dt), int(nblocks), _stream_handle(stream)),
+           "casim_step_host")

@@ -39,6 +39,13 @@ struct Context {
     // compacted-step scratch: post-adjustment state [13][cmp_cap], rates [12][cmp_cap]
     double *d_cstate = nullptr, *d_crates = nullptr;
     int64_t cmp_cap = 0;
+    // host-state pipeline: streams, events and two device buffer sets, each
+    // [14 + 12][pipe_lev][pipe_ld] fields and [8][pipe_ld] surface values
+    bool pipe_ready = false;
+    hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
+    hipEvent_t ev_start = nullptr, ev_in[2] = {}, ev_comp[2] = {}, ev_free[2] = {};
+    double *d_pipe[2] = {};
+    int64_t pipe_ld = 0, pipe_lev = 0;
 };
 
 Context g;
@@ -216,6 +223,52 @@ int ensure_dump(int64_t blocks) {
     return CASIM_OK;
 }
 
+int pipe_create() {
+    if (g.pipe_ready) return CASIM_OK;
+    // default priority on every stream
+    HIP_TRY(hipStreamCreateWithFlags(&g.s_in, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&g.s_comp, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&g.s_out, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&g.ev_start, hipEventDisableTiming));
+    for (int j = 0; j < 2; ++j) {
+        HIP_TRY(hipEventCreateWithFlags(&g.ev_in[j], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&g.ev_comp[j], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&g.ev_free[j], hipEventDisableTiming));
+    }
+    g.pipe_ready = true;
+    return CASIM_OK;
+}
+
+void pipe_destroy() {
+    if (!g.pipe_ready) return;
+    hipDeviceSynchronize();
+    hipStreamDestroy(g.s_in); hipStreamDestroy(g.s_comp); hipStreamDestroy(g.s_out);
+    hipEventDestroy(g.ev_start);
+    for (int j = 0; j < 2; ++j) {
+        hipEventDestroy(g.ev_in[j]); hipEventDestroy(g.ev_comp[j]); hipEventDestroy(g.ev_free[j]);
+        hipFree(g.d_pipe[j]);
+        g.d_pipe[j] = nullptr;
+    }
+    g.pipe_ld = g.pipe_lev = 0;
+    g.pipe_ready = false;
+}
+
+int ensure_pipe(int64_t ld, int64_t nlev) {
+    if (ld <= g.pipe_ld && nlev <= g.pipe_lev) return CASIM_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    const int64_t L = ld > g.pipe_ld ? ld : g.pipe_ld, K = nlev > g.pipe_lev ? nlev : g.pipe_lev;
+    for (int j = 0; j < 2; ++j) {
+        hipFree(g.d_pipe[j]);
+        g.d_pipe[j] = nullptr;
+    }
+    g.pipe_ld = g.pipe_lev = 0;
+    const size_t bytes = sizeof(double) * ((size_t)(CASIM_NIN + CASIM_NTEND) * K * L + (size_t)CASIM_NSFC * L);
+    for (int j = 0; j < 2; ++j) HIP_TRY(hipMalloc(&g.d_pipe[j], bytes));
+    g.pipe_ld = L;
+    g.pipe_lev = K;
+    return CASIM_OK;
+}
+
 int fill_args(const casim_state *s, int64_t ncol, int32_t nlev, double dt, SweepArgs &a) {
     for (int f = 0; f < CASIM_NIN; ++f) a.in[f] = s->in[f];
     for (int f = 0; f < CASIM_NTEND; ++f) a.tend[f] = s->tend[f];
@@ -361,6 +414,81 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
     return CASIM_OK;
 }
 
+int casim_step_host(const casim_host_state *hs, int64_t ncol, int32_t nlev, double dt, int32_t nblocks,
+                    void *stream) {
+    if (!g.init) return CASIM_ENOINIT;
+    if (!hs || nblocks < 0) return CASIM_EINVAL;
+    if (ncol < 0 || nlev < 1 || nlev > CASIM_MAX_NLEV || hs->ld < ncol || !isfinite(dt) || !(dt > 0.0))
+        return CASIM_EINVAL;
+    if (ncol == 0) return CASIM_OK;
+    if (!hs->dz) return CASIM_EINVAL;
+    for (int f = 0; f < CASIM_NIN; ++f)
+        if (!hs->in[f]) return CASIM_EINVAL;
+    for (int f = 0; f < CASIM_NTEND; ++f)
+        if (!hs->tend[f]) return CASIM_EINVAL;
+    for (int f = 0; f < CASIM_NSFC; ++f)
+        if (!hs->sfc[f]) return CASIM_EINVAL;
+    for (int k = 0; k < nlev; ++k)
+        if (!pos_finite(hs->dz[k])) return CASIM_EINVAL;
+    if (nblocks == 0) nblocks = 4;
+    // block width: a multiple of 64 columns
+    int64_t bw = (ncol + nblocks - 1) / nblocks;
+    bw = (bw + 63) / 64 * 64;
+    const int64_t nb = (ncol + bw - 1) / bw;
+    int rc = pipe_create();
+    if (rc) return rc;
+    if ((rc = ensure_pipe(bw, nlev))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(g.ev_start, st));
+    HIP_TRY(hipStreamWaitEvent(g.s_in, g.ev_start, 0));
+    const size_t hp = sizeof(double) * hs->ld, dp = sizeof(double) * g.pipe_ld;
+    const int64_t fld = g.pipe_lev * g.pipe_ld;      // elements per device field
+    for (int64_t b = 0; b < nb; ++b) {
+        const int j = (int)(b & 1);
+        const int64_t c0 = b * bw, nc = ncol - c0 < bw ? ncol - c0 : bw;
+        double *base = g.d_pipe[j];
+        casim_state ds{};
+        for (int f = 0; f < CASIM_NIN; ++f) ds.in[f] = base + f * fld;
+        for (int f = 0; f < CASIM_NTEND; ++f) ds.tend[f] = base + (CASIM_NIN + f) * fld;
+        for (int f = 0; f < CASIM_NSFC; ++f) ds.sfc[f] = base + (CASIM_NIN + CASIM_NTEND) * fld + f * g.pipe_ld;
+        ds.dz = hs->dz;
+        ds.ld = g.pipe_ld;
+        // inbound: buffer set j is free once block b-2's outbound copies are done
+        if (b >= 2) HIP_TRY(hipStreamWaitEvent(g.s_in, g.ev_free[j], 0));
+        for (int f = 0; f < CASIM_NIN; ++f)
+            HIP_TRY(hipMemcpy2DAsync(const_cast<double *>(ds.in[f]), dp, hs->in[f] + c0, hp, sizeof(double) * nc,
+                                     nlev, hipMemcpyHostToDevice, g.s_in));
+        HIP_TRY(hipEventRecord(g.ev_in[j], g.s_in));
+        // step
+        HIP_TRY(hipStreamWaitEvent(g.s_comp, g.ev_in[j], 0));
+        if ((rc = casim_step(&ds, nc, nlev, dt, g.s_comp))) return rc;
+        HIP_TRY(hipEventRecord(g.ev_comp[j], g.s_comp));
+        // outbound
+        HIP_TRY(hipStreamWaitEvent(g.s_out, g.ev_comp[j], 0));
+        for (int f = 0; f < CASIM_NTEND; ++f)
+            HIP_TRY(hipMemcpy2DAsync(hs->tend[f] + c0, hp, ds.tend[f], dp, sizeof(double) * nc, nlev,
+                                     hipMemcpyDeviceToHost, g.s_out));
+        for (int f = 0; f < CASIM_NSFC; ++f)
+            HIP_TRY(hipMemcpyAsync(hs->sfc[f] + c0, ds.sfc[f], sizeof(double) * nc, hipMemcpyDeviceToHost, g.s_out));
+        HIP_TRY(hipEventRecord(g.ev_free[j], g.s_out));
+    }
+    // the outbound stream is in order, so its last event covers every block
+    HIP_TRY(hipStreamWaitEvent(st, g.ev_free[(nb - 1) & 1], 0));
+    return CASIM_OK;
+}
+
+int casim_host_alloc(void **p, size_t bytes) {
+    if (!p) return CASIM_EINVAL;
+    *p = nullptr;
+    HIP_TRY(hipHostMalloc(p, bytes, hipHostMallocDefault));
+    return CASIM_OK;
+}
+
+int casim_host_free(void *p) {
+    if (p) HIP_TRY(hipHostFree(p));
+    return CASIM_OK;
+}
+
 int casim_rates_dump(const casim_state *s, int64_t ncol, int32_t nlev, double dt, uint64_t seed, double keep_prob,
                      int64_t max_samples, float *feat, float *rates, uint16_t *gates, int64_t *n_written,
                      int64_t *n_selected, void *stream) {
@@ -426,6 +554,7 @@ int casim_status(void *stream, casim_step_status *out) {
 }
 
 int casim_finalize(void) {
+    pipe_destroy();
     if (g.d_dz || g.d_status) hipDeviceSynchronize();
     if (g.d_dz) hipFree(g.d_dz);
     if (g.d_status) hipFree(g.d_status);

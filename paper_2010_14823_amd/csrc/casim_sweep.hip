@@ -496,14 +496,15 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
         Ahead v{0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, false};
         const int kk = kk0 - g;
         if (colvalid && kk >= 0) {
+            // the warm configuration never reads the ice, snow and graupel fields
             const int64_t jx = (int64_t)kk * a.ld + col;
             v.T = a.in[0][jx]; v.p = a.in[1][jx]; v.qv = a.in[3][jx];
-            v.qc = a.in[4][jx]; v.qr = a.in[6][jx]; v.qi = a.in[8][jx];
-            v.qs = a.in[10][jx]; v.qg = a.in[12][jx];
+            v.qc = a.in[4][jx]; v.qr = a.in[6][jx];
+            if (!warm) { v.qi = a.in[8][jx]; v.qs = a.in[10][jx]; v.qg = a.in[12][jx]; }
             if (extra) {
                 v.rho = a.in[2][jx];
-                v.nc = a.in[5][jx]; v.nr = a.in[7][jx]; v.ni = a.in[9][jx];
-                v.ns = a.in[11][jx]; v.ng = a.in[13][jx];
+                v.nc = a.in[5][jx]; v.nr = a.in[7][jx];
+                if (!warm) { v.ni = a.in[9][jx]; v.ns = a.in[11][jx]; v.ng = a.in[13][jx]; }
                 v.extra = true;
             }
         }
@@ -551,8 +552,8 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
                 w.nc = cur.nc; w.nr = cur.nr; w.ni = cur.ni; w.ns = cur.ns; w.ng = cur.ng;
             } else {
                 rho = a.in[2][ix];
-                w.nc = a.in[5][ix]; w.nr = a.in[7][ix]; w.ni = a.in[9][ix];
-                w.ns = a.in[11][ix]; w.ng = a.in[13][ix];
+                w.nc = a.in[5][ix]; w.nr = a.in[7][ix];
+                if (!warm) { w.ni = a.in[9][ix]; w.ns = a.in[11][ix]; w.ng = a.in[13][ix]; }
             }
         }
         nxt = load_ahead(k0 - L, col_busy);
