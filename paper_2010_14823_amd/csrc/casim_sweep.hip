@@ -63,9 +63,18 @@ template <> struct Mth<float> {
 template <class R>
 __device__ __forceinline__ R clampv(R x, R lo, R hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
-// a / b in the rate precision: reciprocal-based in binary64, plain in binary32
-__device__ __forceinline__ double rdiv(double a, double b) { return a * rcp64(b); }
-__device__ __forceinline__ float rdiv(float a, float b) { return a / b; }
+// The step reads each input and writes each tendency exactly once: streaming
+// (non-temporal) accesses keep them from displacing other lines in the caches.
+__device__ __forceinline__ double ldnt(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void stnt(double *p, double v) { __builtin_nontemporal_store(v, p); }
+
+// 1/b and a/b in the rate precision: the refined reciprocal in binary64, the
+// hardware reciprocal (1 ulp) in binary32, whose rates only need binary32
+// accuracy
+__device__ __forceinline__ double rrcp(double b) { return rcp64(b); }
+__device__ __forceinline__ float rrcp(float b) { return 1.0f / b; }
+template <class R>
+__device__ __forceinline__ R rdiv(R a, R b) { return a * rrcp(b); }
 
 // Working state of one point: values (w) and accumulated increments (d).
 struct Pt {
@@ -85,6 +94,14 @@ __device__ __forceinline__ double esat_ice(const DevParams &P, double T) {
 }
 __device__ __forceinline__ double q_of_e(const DevParams &P, double e, double p) {
     return P.eps * e * rcp64(p - P.one_m_eps * e);
+}
+// q_v / q_sat(e) - 1 with one reciprocal (q_sat = eps e / (p - (1 - eps) e)).
+__device__ __forceinline__ double sat_m1(const DevParams &P, double qv, double e, double p) {
+    return qv * (p - P.one_m_eps * e) * rcp64(P.eps * e) - 1.0;
+}
+// q_v > q_sat(e) without a division (p - (1 - eps) e > 0 for any e below p).
+__device__ __forceinline__ bool supersat(const DevParams &P, double qv, double e, double p) {
+    return qv * (p - P.one_m_eps * e) > P.eps * e;
 }
 
 // ---- clean-up and instant phase changes ----------------------------------
@@ -146,17 +163,20 @@ __device__ __forceinline__ bool satadj(const DevParams &P, int iters, Pt &w, Pt 
                                        double T_in, double es_in, double &es_out) {
     double es0 = (w.T == T_in) ? es_in : esat_liq(P, w.T);
     es_out = es0;
-    if (!(w.qv > q_of_e(P, es0, p) || w.qc > 0.0)) return false;
+    if (!(supersat(P, w.qv, es0, p) || w.qc > 0.0)) return false;
+    // f/f' with D = p - (1 - eps) e_s multiplied through by D^2, so that one
+    // reciprocal serves both q_sat and the quotient:
+    //   f = cp delta - Lv (qv - eps e_s / D),  f' = cp + Lv eps e_s p bc / (D^2 (Tc + c)^2)
     double delta = 0.0, es = es0;
     for (int it = 0; it < iters; ++it) {
         const double Tc = (w.T + delta) - P.T_0;
         const double rtc = rcp64(Tc + P.esl_c);
         if (it > 0) es = P.esl_a * exp64(P.esl_b * Tc * rtc);
-        const double rden = rcp64(p - P.one_m_eps * es);
-        const double qs = P.eps * es * rden;
-        const double f = P.cp * delta - P.L_v * (w.qv - qs);
-        const double fp = P.cp + P.L_v * qs * (p * rden) * P.esl_bc * (rtc * rtc);
-        delta -= f * rcp64(fp);
+        const double D = p - P.one_m_eps * es;
+        const double Les = P.L_v * P.eps * es;
+        const double num = D * ((P.cp * delta - P.L_v * w.qv) * D + Les);
+        const double den = P.cp * (D * D) + Les * p * P.esl_bc * (rtc * rtc);
+        delta -= num * rcp64(den);
     }
     const double T1 = w.T + delta;
     const double es1 = esat_liq(P, T1);
@@ -204,14 +224,14 @@ __device__ __forceinline__ void rates(const DevParams &P, bool warm, const Pt &w
     const bool revp = rP && w.qc == 0.0;
     const bool dep = cold && (iP || sP);
     // saturation ratios in binary64
-    const double Sl_m1 = w.qv * rcp64(q_of_e(P, esl, p)) - 1.0;
+    const double Sl_m1 = sat_m1(P, w.qv, esl, p);
     double esi = 0.0, Si_m1 = 0.0;
     if (dep) {
         esi = esat_ice(P, w.T);
-        Si_m1 = w.qv * rcp64(q_of_e(P, esi, p)) - 1.0;
+        Si_m1 = sat_m1(P, w.qv, esi, p);
     }
 
-    const R T = R(w.T), rh = R(rho), lrh = R(ln_rho), rf = R(rfac);
+    const R T = R(w.T), irh = rrcp(R(rho)), lrh = R(ln_rho), rf = R(rfac);
     const R dT0 = T - R(P.T_0);
     // ln lambda, clamped to the mean-diameter bounds, and lambda^-1
     R lnqc = R(0), lnqr = R(0), llr = R(0), llg = R(0), lls = R(0);
@@ -246,14 +266,18 @@ __device__ __forceinline__ void rates(const DevParams &P, bool warm, const Pt &w
     if (do_revp || dep) {
         const R KRT2 = R(P.K_a) * R(P.R_v) * T * T;
         const R Dv = R(P.Dv0) * M::exp(R(P.Dv_exp) * M::log(T * R(1.0 / P.T_0))) * rdiv(R(1e5), R(p));
+        // G = 1 / (L^2/(K R_v T^2) + R_v T/(D_v e)) = K R_v T^2 D_v e / (L^2 D_v e + R_v T K R_v T^2)
+        const R RvT_KRT2 = R(P.R_v) * T * KRT2;
         if (do_revp) {
-            const R Gl = rdiv(R(1), rdiv(R(P.L_v) * R(P.L_v), KRT2) + rdiv(R(P.R_v) * T, Dv * R(esl)));
+            const R De = Dv * R(esl);
+            const R Gl = rdiv(KRT2 * De, R(P.L_v) * R(P.L_v) * De + RvT_KRT2);
             r[REVP] = R(P.two_pi) * Gl * R(-Sl_m1) * R(w.nr) * ilr;
         }
         if (dep) {
-            const R Gi = rdiv(R(1), rdiv(R(P.L_s) * R(P.L_s), KRT2) + rdiv(R(P.R_v) * T, Dv * R(esi)));
+            const R De = Dv * R(esi);
+            const R Gi = rdiv(KRT2 * De, R(P.L_s) * R(P.L_s) * De + RvT_KRT2);
             if (iP) r[DEPI] = R(P.two_pi) * Gi * R(Si_m1) * R(w.ni) * ili;
-            if (sP) r[DEPS] = rdiv(R(P.two_pi) * Gi * R(Si_m1) * R(P.N0_s), rh) * (ils * ils);
+            if (sP) r[DEPS] = R(P.two_pi) * Gi * R(Si_m1) * R(P.N0_s) * irh * (ils * ils);
         }
     }
     if (cold) {
@@ -272,7 +296,7 @@ __device__ __forceinline__ void rates(const DevParams &P, bool warm, const Pt &w
         }
     }
     if (hot && (sP || gP)) {
-        const R melt = rdiv(R(P.two_pi) * R(P.K_a) * dT0, rh * R(P.L_f));
+        const R melt = R(P.two_pi) * R(P.K_a) * dT0 * irh * R(1.0 / P.L_f);
         if (sP) r[SMLT] = melt * R(P.N0_s) * (ils * ils);
         if (gP) r[GMLT] = melt * R(P.N0_g) * (ilg * ilg);
     }
@@ -348,7 +372,7 @@ __device__ __forceinline__ unsigned gate_bits(const DevParams &P, bool warm, con
     unsigned g = 0;
     if (cP && w.nc > 0.0) g |= 1u << AUTO;
     if (cP && rP) g |= 1u << ACCR;
-    if (rP && w.qc == 0.0 && w.qv * rcp64(q_of_e(P, esl, p)) - 1.0 < 0.0) g |= 1u << REVP;
+    if (rP && w.qc == 0.0 && sat_m1(P, w.qv, esl, p) < 0.0) g |= 1u << REVP;
     if (iP && cold) g |= (1u << DEPI);
     if (sP && cold) g |= (1u << DEPS);
     if (iP && cold && w.qi > P.q_i0) g |= 1u << IAUT;
@@ -358,7 +382,7 @@ __device__ __forceinline__ unsigned gate_bits(const DevParams &P, bool warm, con
     if (rP && cold) g |= 1u << FRZR;
     if (sP && hot) g |= 1u << SMLT;
     if (gP && hot) g |= 1u << GMLT;
-    if (cold && (iP || sP) && w.qv * rcp64(q_of_e(P, esat_ice(P, w.T), p)) - 1.0 > 0.0) g |= CASIM_GATE_SUPERSAT_ICE;
+    if (cold && (iP || sP) && sat_m1(P, w.qv, esat_ice(P, w.T), p) > 0.0) g |= CASIM_GATE_SUPERSAT_ICE;
     return g;
 }
 
@@ -458,7 +482,7 @@ enum { VAR_GENERIC = 0, VAR_COLD = 1, VAR_WARM = 2 };
 enum { SRC_PLAIN = 0, SRC_NET = 1, SRC_DENSE = 2 };
 
 template <bool MIX, int VAR, int C, int SRC>
-__global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) {
+__global__ __launch_bounds__(256, 3) void sweep_kernel(DevParams Prt, SweepArgs a) {
     using R = typename std::conditional<MIX, float, double>::type;
     constexpr int L = kWave / C;
     constexpr bool FAST = VAR != VAR_GENERIC;
@@ -498,13 +522,13 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
         if (colvalid && kk >= 0) {
             // the warm configuration never reads the ice, snow and graupel fields
             const int64_t jx = (int64_t)kk * a.ld + col;
-            v.T = a.in[0][jx]; v.p = a.in[1][jx]; v.qv = a.in[3][jx];
-            v.qc = a.in[4][jx]; v.qr = a.in[6][jx];
-            if (!warm) { v.qi = a.in[8][jx]; v.qs = a.in[10][jx]; v.qg = a.in[12][jx]; }
+            v.T = ldnt(a.in[0] + jx); v.p = ldnt(a.in[1] + jx); v.qv = ldnt(a.in[3] + jx);
+            v.qc = ldnt(a.in[4] + jx); v.qr = ldnt(a.in[6] + jx);
+            if (!warm) { v.qi = ldnt(a.in[8] + jx); v.qs = ldnt(a.in[10] + jx); v.qg = ldnt(a.in[12] + jx); }
             if (extra) {
-                v.rho = a.in[2][jx];
-                v.nc = a.in[5][jx]; v.nr = a.in[7][jx];
-                if (!warm) { v.ni = a.in[9][jx]; v.ns = a.in[11][jx]; v.ng = a.in[13][jx]; }
+                v.rho = ldnt(a.in[2] + jx);
+                v.nc = ldnt(a.in[5] + jx); v.nr = ldnt(a.in[7] + jx);
+                if (!warm) { v.ni = ldnt(a.in[9] + jx); v.ns = ldnt(a.in[11] + jx); v.ng = ldnt(a.in[13] + jx); }
                 v.extra = true;
             }
         }
@@ -527,8 +551,8 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
             act = (w.qc > 0.0) | (w.qr > 0.0) | (!warm & ((w.qi > 0.0) | (w.qs > 0.0) | (w.qg > 0.0)));
             es_l = esat_liq(P, w.T);
             // a condensate-free point changes only if supersaturated
-            if (!act && do_sat) act = w.qv > q_of_e(P, es_l, p);
-            if (!act && do_adj && !warm && w.T < P.T_nuc) act = w.qv > q_of_e(P, esat_ice(P, w.T), p);
+            if (!act && do_sat) act = supersat(P, w.qv, es_l, p);
+            if (!act && do_adj && !warm && w.T < P.T_nuc) act = supersat(P, w.qv, esat_ice(P, w.T), p);
         }
         const double T_in = w.T;
         const unsigned long long bal = __ballot((int)act);
@@ -536,7 +560,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
             nxt = load_ahead(k0 - L, false);
             if (vp) {
 #pragma unroll
-                for (int f = 0; f < CASIM_NTEND; ++f) a.tend[f][ix] = 0.0;
+                for (int f = 0; f < CASIM_NTEND; ++f) stnt(a.tend[f] + ix, 0.0);
             }
             continue;
         }
@@ -556,7 +580,11 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
                 if (!warm) { w.ni = a.in[9][ix]; w.ns = a.in[11][ix]; w.ng = a.in[13][ix]; }
             }
         }
-        nxt = load_ahead(k0 - L, col_busy);
+        // The binary64 kernel issues the next chunk's loads before the point
+        // physics (longest cover of their latency); the mixed kernel issues them
+        // after it, which keeps them out of the registers of the rate block and
+        // lets the kernel fit 128 VGPRs (4 wavefronts per SIMD; measured faster).
+        if constexpr (!MIX) nxt = load_ahead(k0 - L, col_busy);
         if (need) ln_rho = log64(rho);
         const double rfac = ::sqrt(P.rho_0 * rcp64(rho));
         if (act) {
@@ -606,6 +634,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
                 }
             }
         }
+        if constexpr (MIX) nxt = load_ahead(k0 - L, col_busy);
         bool out_nz = false;
         if (do_sed) {
             double inv_rdz = 0.0;
@@ -629,7 +658,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(DevParams Prt, SweepArgs a) 
                                   d.qs * inv_dt, d.ns * inv_dt, d.qg * inv_dt, d.ng * inv_dt};
             double sum = 0.0;
 #pragma unroll
-            for (int f = 0; f < CASIM_NTEND; ++f) { a.tend[f][ix] = o[f]; sum += ::fabs(o[f]); }
+            for (int f = 0; f < CASIM_NTEND; ++f) { stnt(a.tend[f] + ix, o[f]); sum += ::fabs(o[f]); }
             nonfinite += ::isfinite(sum) ? 0u : 1u;
         }
     }
@@ -672,8 +701,8 @@ __global__ __launch_bounds__(256) void point_kernel(DevParams Prt, PointArgs pa)
         w.qs = a.in[10][ix]; w.qg = a.in[12][ix];
         act = (w.qc > 0.0) | (w.qr > 0.0) | (!warm & ((w.qi > 0.0) | (w.qs > 0.0) | (w.qg > 0.0)));
         es_l = esat_liq(P, w.T);
-        if (!act && do_sat) act = w.qv > q_of_e(P, es_l, p);
-        if (!act && do_adj && !warm && w.T < P.T_nuc) act = w.qv > q_of_e(P, esat_ice(P, w.T), p);
+        if (!act && do_sat) act = supersat(P, w.qv, es_l, p);
+        if (!act && do_adj && !warm && w.T < P.T_nuc) act = supersat(P, w.qv, esat_ice(P, w.T), p);
     }
     // slotted passes take every active point; the rate dump draws a sample
     const bool slotted = pa.mode == POINT_SURR || pa.mode == POINT_CSTATE;
