@@ -515,11 +515,15 @@ __global__ __launch_bounds__(256, 3) void sweep_kernel(DevParams Prt, SweepArgs 
     // column is usually busy too).  A lane that turns busy without them loads
     // them itself.  Loading ahead keeps a chunk from waiting on the previous
     // chunk's stores, which share the vector-memory counter with loads.
-    struct Ahead { double T, p, qv, qc, qr, qi, qs, qg, rho, nc, nr, ni, ns, ng; bool extra; };
+    // With rates from a slot (SRC_NET, SRC_DENSE) the point's slot index comes
+    // one chunk ahead too, which takes one of the two dependent loads of a
+    // slotted point off the chunk's critical path.
+    struct Ahead { double T, p, qv, qc, qr, qi, qs, qg, rho, nc, nr, ni, ns, ng; bool extra; int slot; };
     auto load_ahead = [&](int kk0, bool extra) {
-        Ahead v{0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, false};
+        Ahead v{0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, false, -1};
         const int kk = kk0 - g;
         if (colvalid && kk >= 0) {
+            if constexpr (SRC != SRC_PLAIN) v.slot = a.sur_idx[(int64_t)kk * a.ncol + col];
             // the warm configuration never reads the ice, snow and graupel fields
             const int64_t jx = (int64_t)kk * a.ld + col;
             v.T = ldnt(a.in[0] + jx); v.p = ldnt(a.in[1] + jx); v.qv = ldnt(a.in[3] + jx);
@@ -587,6 +591,7 @@ __global__ __launch_bounds__(256, 3) void sweep_kernel(DevParams Prt, SweepArgs 
         if constexpr (!MIX) nxt = load_ahead(k0 - L, col_busy);
         if (need) ln_rho = log64(rho);
         const double rfac = ::sqrt(P.rho_0 * rcp64(rho));
+        const int slot = cur.slot;
         if (act) {
             if (do_adj) adjust(P, warm, w, d, p, rho);
             double es_now = es_l;
@@ -597,7 +602,6 @@ __global__ __launch_bounds__(256, 3) void sweep_kernel(DevParams Prt, SweepArgs 
                 bool plain = SRC == SRC_PLAIN;
                 if constexpr (SRC == SRC_DENSE) {
                     // no slot: every rate gate is closed and all 12 rates are zero
-                    const int slot = a.sur_idx[(int64_t)k * a.ncol + col];
                     if (slot >= 0) {
                         double rr[12];
 #pragma unroll
@@ -608,7 +612,6 @@ __global__ __launch_bounds__(256, 3) void sweep_kernel(DevParams Prt, SweepArgs 
                 if constexpr (SRC == SRC_NET) {
                     plain = true;
                     // network rates for this point, unless it falls back
-                    const int slot = a.sur_idx[(int64_t)k * a.ncol + col];
                     if (slot >= 0) {
                         bool use = !a.sur_fallback[slot];
                         if (use) {
