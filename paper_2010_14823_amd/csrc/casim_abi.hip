@@ -39,6 +39,15 @@ struct Context {
     // compacted-step scratch: post-adjustment state [13][cmp_cap], rates [12][cmp_cap]
     double *d_cstate = nullptr, *d_crates = nullptr;
     int64_t cmp_cap = 0;
+    // tile launch order: per-tile activity of the last step and the order
+    // derived from it; the activity is reused only for the same domain
+    int32_t *d_busy = nullptr, *d_order = nullptr;
+    int64_t tile_cap = 0;
+    bool hist = false;
+    const void *hist_in0 = nullptr;
+    int64_t hist_ncol = 0, hist_ld = 0;
+    int32_t hist_nlev = 0, hist_mode = -1, hist_warm = -1;
+    int reserve_tiles = 0;
     // host-state pipeline: streams, events and two device buffer sets, each
     // [14 + 12][pipe_lev][pipe_ld] fields and [8][pipe_ld] surface values
     bool pipe_ready = false;
@@ -203,6 +212,11 @@ int ensure_cmp(int64_t npts) {
     if (npts <= g.cmp_cap) return CASIM_OK;
     HIP_TRY(hipDeviceSynchronize());
     hipFree(g.d_cstate); hipFree(g.d_crates);
+    hipFree(g.d_busy); hipFree(g.d_order);
+    g.d_busy = g.d_order = nullptr;
+    g.tile_cap = 0;
+    g.hist = false;
+    g.reserve_tiles = 0;
     g.d_cstate = nullptr; g.d_crates = nullptr;
     g.cmp_cap = 0;
     HIP_TRY(hipMalloc(&g.d_cstate, sizeof(double) * kCmpState * npts));
@@ -269,6 +283,53 @@ int ensure_pipe(int64_t ld, int64_t nlev) {
     return CASIM_OK;
 }
 
+int ensure_tiles(int64_t ntiles) {
+    if (ntiles <= g.tile_cap) return CASIM_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    hipFree(g.d_busy); hipFree(g.d_order);
+    g.d_busy = g.d_order = nullptr;
+    g.tile_cap = 0;
+    g.hist = false;
+    HIP_TRY(hipMalloc(&g.d_busy, sizeof(int32_t) * ntiles));
+    HIP_TRY(hipMalloc(&g.d_order, sizeof(int32_t) * ntiles));
+    g.tile_cap = ntiles;
+    return CASIM_OK;
+}
+
+// Tile order for this step (from the last step's activity when it ran on the
+// same domain) and activity recording for the next.  CASIM_TILE_ORDER=0 in
+// the environment keeps the identity order.
+int plan_tiles(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, hipStream_t st) {
+    const int C = sweep_columns_per_wave(ncol);
+    const int64_t ntiles = (ncol + C - 1) / C;
+    int rc = ensure_tiles(ntiles);
+    if (rc) return rc;
+    if (!g.reserve_tiles) {
+        int cus = 0;
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g.device));
+        g.reserve_tiles = 12 * (cus > 0 ? cus : 1);       // one dispatch round: 3 wavefronts x 4 SIMDs per CU
+    }
+    static const int enabled = [] { const char *e = getenv("CASIM_TILE_ORDER"); return e ? atoi(e) : 1; }();
+    const bool same = g.hist && g.hist_in0 == (const void *)s->in[0] && g.hist_ncol == ncol &&
+                      g.hist_ld == s->ld && g.hist_nlev == nlev && g.hist_mode == g.c.mode &&
+                      g.hist_warm == g.c.warm;
+    a.ntiles = ntiles;
+    a.tile_busy = g.d_busy;
+    a.order = nullptr;
+    if (same && enabled) {
+        HIP_TRY(launch_tile_order(g.d_busy, ntiles, g.reserve_tiles, g.d_order, st));
+        a.order = g.d_order;
+    }
+    g.hist = true;
+    g.hist_in0 = s->in[0];
+    g.hist_ncol = ncol;
+    g.hist_ld = s->ld;
+    g.hist_nlev = nlev;
+    g.hist_mode = g.c.mode;
+    g.hist_warm = g.c.warm;
+    return CASIM_OK;
+}
+
 int fill_args(const casim_state *s, int64_t ncol, int32_t nlev, double dt, SweepArgs &a) {
     for (int f = 0; f < CASIM_NIN; ++f) a.in[f] = s->in[f];
     for (int f = 0; f < CASIM_NTEND; ++f) a.tend[f] = s->tend[f];
@@ -289,6 +350,9 @@ int fill_args(const casim_state *s, int64_t ncol, int32_t nlev, double dt, Sweep
     a.sur_f_min = g.t.sur_f_min;
     a.cmp_rates = nullptr;
     a.cmp_ld = 0;
+    a.order = nullptr;
+    a.tile_busy = nullptr;
+    a.ntiles = 0;
     return CASIM_OK;
 }
 
@@ -410,6 +474,7 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
         a.cmp_rates = g.d_crates;
         a.cmp_ld = g.cmp_cap;
     }
+    if ((rc = plan_tiles(s, ncol, nlev, a, st))) return rc;
     HIP_TRY(launch_sweep(g.P, g.fast, a, st));
     return CASIM_OK;
 }
@@ -565,6 +630,11 @@ int casim_finalize(void) {
     g.dump_blocks = 0;
     hipFree(g.d_idx); hipFree(g.d_feat); hipFree(g.d_rates); hipFree(g.d_gates); hipFree(g.d_fb); hipFree(g.d_count);
     hipFree(g.d_cstate); hipFree(g.d_crates);
+    hipFree(g.d_busy); hipFree(g.d_order);
+    g.d_busy = g.d_order = nullptr;
+    g.tile_cap = 0;
+    g.hist = false;
+    g.reserve_tiles = 0;
     g.d_idx = nullptr; g.d_feat = nullptr; g.d_rates = nullptr; g.d_gates = nullptr; g.d_fb = nullptr;
     g.d_count = nullptr; g.d_cstate = nullptr; g.d_crates = nullptr;
     g.idx_cap = g.sur_cap = g.cmp_cap = 0;

@@ -116,6 +116,11 @@ struct SweepArgs {
     // compacted binary64 mode: rates[j * cmp_ld + slot] from the dense rate kernel
     const double *cmp_rates;
     int64_t cmp_ld;
+    // tiles (C columns each): launch order (null: wavefront w takes tile w)
+    // and, per tile, whether any chunk was busy (written for the next step)
+    const int32_t *order;
+    int32_t *tile_busy;
+    int64_t ntiles;
 };
 
 // Point-parallel passes over (k, column) in point order p = k*ncol + c.
@@ -153,6 +158,12 @@ constexpr int kCmpState = 13;
 // Launchers (casim_sweep.hip).  `fast` selects the kernels compiled with
 // kDefaultParams.  Return the launch's hipError_t.
 hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream);
+// Columns per wavefront tile the sweep uses for ncol columns.
+int sweep_columns_per_wave(int64_t ncol);
+// Tile launch order from the previous step's per-tile activity: busy tiles
+// and most clear ones in index order, the last `reserve` clear tiles at the end.
+hipError_t launch_tile_order(const int32_t *busy, int64_t ntiles, int64_t reserve, int32_t *order,
+                             hipStream_t stream);
 hipError_t launch_apply(const SweepArgs &a, double dt, hipStream_t stream);
 hipError_t launch_math(const double *x, int64_t n, double *e, double *l, hipStream_t stream);
 hipError_t launch_points(const DevParams &P, bool fast, const PointArgs &pa, hipStream_t stream);

@@ -482,7 +482,7 @@ enum { VAR_GENERIC = 0, VAR_COLD = 1, VAR_WARM = 2 };
 enum { SRC_PLAIN = 0, SRC_NET = 1, SRC_DENSE = 2 };
 
 template <bool MIX, int VAR, int C, int SRC>
-__global__ __launch_bounds__(256, 3) void sweep_kernel(DevParams Prt, SweepArgs a) {
+__global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void sweep_kernel(DevParams Prt, SweepArgs a) {
     using R = typename std::conditional<MIX, float, double>::type;
     constexpr int L = kWave / C;
     constexpr bool FAST = VAR != VAR_GENERIC;
@@ -492,8 +492,18 @@ __global__ __launch_bounds__(256, 3) void sweep_kernel(DevParams Prt, SweepArgs 
     const int wib = threadIdx.x / kWave;
     const int g = lane / C, c = lane % C;
     double *lds = lds_all + (size_t)wib * (a.nslots + 8) * C;
-    const int64_t col = ((int64_t)blockIdx.x * (blockDim.x / kWave) + wib) * C + c;
+    // wavefront -> tile of C columns: the launch order derived from the
+    // previous step's activity, else the identity (a corrupt entry falls back
+    // to the identity, so no wavefront can leave the domain)
+    const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x / kWave) + wib;
+    int64_t tile = wave_id;
+    if (a.order && wave_id < a.ntiles) {
+        const int64_t o = a.order[wave_id];
+        tile = (o >= 0 && o < a.ntiles) ? o : wave_id;
+    }
+    const int64_t col = tile * C + c;
     const bool colvalid = col < a.ncol;
+    bool wave_busy = false;
     const double dt = a.dt, inv_dt = 1.0 / dt;
     const bool warm = FAST ? VAR == VAR_WARM : a.warm != 0;
     const int ncat = warm ? 1 : 4;
@@ -568,6 +578,7 @@ __global__ __launch_bounds__(256, 3) void sweep_kernel(DevParams Prt, SweepArgs 
             }
             continue;
         }
+        wave_busy = true;
         unsigned long long colbits = carry_cols;
 #pragma unroll
         for (int gg = 0; gg < L; ++gg) colbits |= (bal >> (gg * C)) & cmask;
@@ -668,6 +679,10 @@ __global__ __launch_bounds__(256, 3) void sweep_kernel(DevParams Prt, SweepArgs 
     if (surf_lane) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) a.sfc[j][col] = psurf[j * C];
+    }
+    if (a.tile_busy && lane == 0) {            // lane 0 holds column c = 0 of the tile
+        const int64_t t = col / C;
+        if (t < a.ntiles) a.tile_busy[t] = wave_busy ? 1 : 0;
     }
     if (newton_bad) atomicAdd(&a.status[0], (unsigned long long)newton_bad);
     if (nonfinite) atomicAdd(&a.status[1], (unsigned long long)nonfinite);
@@ -853,6 +868,62 @@ __global__ __launch_bounds__(256) void scan_kernel(const int64_t *counts, int64_
     for (int64_t i = b; i < e; ++i) { offsets[i] = acc; acc += counts[i]; }
 }
 
+// Launch order of the sweep's tiles for the next step.  The paper found a
+// guided schedule best for the unequal work of its columns (Sec. IV); on the
+// GPU the hardware hands out wavefronts in launch order, so a busy tile
+// launched in the last round would end the kernel late.  Order: every tile
+// that was busy in the previous step and the clear tiles except the last
+// `reserve` of them, in index order (so busy and clear tiles stay mixed for
+// the overlap of arithmetic and streaming), then those reserved clear tiles,
+// which fill the last dispatch round.  One block; busy[i] in {0, 1}.
+__global__ __launch_bounds__(1024) void tile_order_kernel(const int32_t *busy, int64_t n, int64_t reserve,
+                                                          int32_t *order) {
+    __shared__ int64_t part[1024];
+    __shared__ int64_t total_s;
+    const int t = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t b = (int64_t)t * per < n ? (int64_t)t * per : n;
+    const int64_t e = b + per < n ? b + per : n;
+    int64_t nclear = 0;
+    for (int64_t i = b; i < e; ++i) nclear += busy[i] == 0;
+    part[t] = nclear;
+    __syncthreads();
+    if (t == 0) {                       // part[j] = clear tiles after range j
+        int64_t acc = 0;
+        for (int j = 1023; j >= 0; --j) { const int64_t v = part[j]; part[j] = acc; acc += v; }
+    }
+    __syncthreads();
+    const int64_t after = part[t];
+    // reserved tiles of this range: clear, with at most `reserve` clear tiles at or after them
+    int64_t ns = 0, suffix = after;
+    for (int64_t i = e - 1; i >= b; --i)
+        if (busy[i] == 0 && ++suffix <= reserve) ++ns;
+    __syncthreads();
+    part[t] = ns;
+    __syncthreads();
+    if (t == 0) {                       // part[j] = reserved tiles before range j
+        int64_t acc = 0;
+        for (int j = 0; j < 1024; ++j) { const int64_t v = part[j]; part[j] = acc; acc += v; }
+        total_s = acc;
+    }
+    __syncthreads();
+    int64_t rank = part[t], clear_seen = 0;
+    const int64_t first_reserved = n - total_s;
+    for (int64_t i = b; i < e; ++i) {
+        const bool clear = busy[i] == 0;
+        const bool reserved = clear && after + (nclear - clear_seen) <= reserve;
+        order[reserved ? first_reserved + rank : i - rank] = (int32_t)i;
+        rank += reserved;
+        clear_seen += clear;
+    }
+}
+
+hipError_t launch_tile_order(const int32_t *busy, int64_t ntiles, int64_t reserve, int32_t *order,
+                             hipStream_t stream) {
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, stream, busy, ntiles, reserve, order);
+    return hipGetLastError();
+}
+
 // X += dt * tend for the 12 prognostic fields; q and n clipped at 0.
 __global__ __launch_bounds__(256) void apply_kernel(SweepArgs a, double dt, int64_t npts) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -902,7 +973,7 @@ hipError_t launch_var(int var, int C, dim3 grid, dim3 block, size_t lds, hipStre
 // Columns per wavefront.  16-column tiles (16 x 4 levels, one 128-byte row
 // per level) measured best on the large domains; narrower tiles keep at
 // least 2048 wavefronts (two per SIMD) on small ones.
-static int pick_columns_per_wave(int64_t ncol) {
+int sweep_columns_per_wave(int64_t ncol) {
     const int forced = env_int("CASIM_COLS_PER_WAVE", 0);
     if (forced == 4 || forced == 8 || forced == 16 || forced == 32 || forced == 64) return forced;
     if (ncol / 16 >= 2048) return 16;
@@ -911,7 +982,7 @@ static int pick_columns_per_wave(int64_t ncol) {
 }
 
 hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream) {
-    const int C = pick_columns_per_wave(a.ncol);
+    const int C = sweep_columns_per_wave(a.ncol);
     // narrow tiles: enough wavefronts per block to cover whole 128-byte rows,
     // so the halves of a line are fetched by one CU
     int wpb = env_int("CASIM_WAVES_PER_BLOCK", C >= 16 ? 1 : 16 / C);
@@ -921,6 +992,7 @@ hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipSt
     while (wpb > 1 && lds > 65536) { --wpb; lds = (size_t)wpb * per_wave; }
     if (lds > 65536) return hipErrorInvalidValue;
     const int64_t waves = (a.ncol + C - 1) / C;
+    if ((a.order || a.tile_busy) && a.ntiles != waves) return hipErrorInvalidValue;
     const int64_t blocks = (waves + wpb - 1) / wpb;
     const dim3 grid((unsigned)blocks), block(wpb * kWave);
     // the compiled-in variants need the default constants and all stages
