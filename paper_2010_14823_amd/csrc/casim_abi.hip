@@ -396,6 +396,7 @@ int casim_init(const casim_constants *c, const casim_thresholds *t) {
     g.t = *t;
     g.P = derive(*c, *t, gamma_table(*c));
     g.fast = defaults_apply(*c, *t);
+    g.hist = false;                         // the next step runs in index order
     g.init = true;
     return CASIM_OK;
 }

@@ -876,39 +876,44 @@ __global__ __launch_bounds__(256) void scan_kernel(const int64_t *counts, int64_
 // `reserve` of them, in index order (so busy and clear tiles stay mixed for
 // the overlap of arithmetic and streaming), then those reserved clear tiles,
 // which fill the last dispatch round.  One block; busy[i] in {0, 1}.
+// Exclusive prefix sum of one value per thread over a 1024-thread block
+// (Hillis-Steele in LDS); *total receives the sum.
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *buf, int64_t *total) {
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t add = t >= off ? buf[t - off] : 0;
+        __syncthreads();
+        buf[t] += add;
+        __syncthreads();
+    }
+    const int64_t incl = buf[t];
+    if (t == 1023) *total = incl;
+    __syncthreads();
+    return incl - v;
+}
+
 __global__ __launch_bounds__(1024) void tile_order_kernel(const int32_t *busy, int64_t n, int64_t reserve,
                                                           int32_t *order) {
-    __shared__ int64_t part[1024];
-    __shared__ int64_t total_s;
+    __shared__ int64_t buf[1024];
+    __shared__ int64_t total;
     const int t = threadIdx.x;
     const int64_t per = (n + 1023) / 1024;
     const int64_t b = (int64_t)t * per < n ? (int64_t)t * per : n;
     const int64_t e = b + per < n ? b + per : n;
     int64_t nclear = 0;
     for (int64_t i = b; i < e; ++i) nclear += busy[i] == 0;
-    part[t] = nclear;
-    __syncthreads();
-    if (t == 0) {                       // part[j] = clear tiles after range j
-        int64_t acc = 0;
-        for (int j = 1023; j >= 0; --j) { const int64_t v = part[j]; part[j] = acc; acc += v; }
-    }
-    __syncthreads();
-    const int64_t after = part[t];
+    // clear tiles after this range = all clear tiles - clear tiles up to its end
+    const int64_t before = block_exclusive_scan(nclear, buf, &total);
+    const int64_t after = total - before - nclear;
     // reserved tiles of this range: clear, with at most `reserve` clear tiles at or after them
     int64_t ns = 0, suffix = after;
     for (int64_t i = e - 1; i >= b; --i)
         if (busy[i] == 0 && ++suffix <= reserve) ++ns;
-    __syncthreads();
-    part[t] = ns;
-    __syncthreads();
-    if (t == 0) {                       // part[j] = reserved tiles before range j
-        int64_t acc = 0;
-        for (int j = 0; j < 1024; ++j) { const int64_t v = part[j]; part[j] = acc; acc += v; }
-        total_s = acc;
-    }
-    __syncthreads();
-    int64_t rank = part[t], clear_seen = 0;
-    const int64_t first_reserved = n - total_s;
+    int64_t rank = block_exclusive_scan(ns, buf, &total);     // reserved tiles before this range
+    const int64_t first_reserved = n - total;
+    int64_t clear_seen = 0;
     for (int64_t i = b; i < e; ++i) {
         const bool clear = busy[i] == 0;
         const bool reserved = clear && after + (nclear - clear_seen) <= reserve;
