@@ -194,7 +194,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the column step needs no exchange between GPUs "
-              "and this build runs on a single MI355X; use --gpus 1", file=sys.stderr)
+              "and this benchmark runs on a single MI355X; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
