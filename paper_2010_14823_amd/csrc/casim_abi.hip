@@ -298,17 +298,44 @@ int ensure_tiles(int64_t ntiles) {
 
 // Tile order for this step (from the last step's activity when it ran on the
 // same domain) and activity recording for the next.  CASIM_TILE_ORDER=0 in
-// the environment keeps the identity order.
+// the environment keeps the identity order; CASIM_XCDS sets the number of
+// XCDs the block renumbering assumes (default 8, the XCDs of an MI355X; 1
+// turns it off) and CASIM_XCD_GROUP its group size in blocks.
 int plan_tiles(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, hipStream_t st) {
-    const int C = sweep_columns_per_wave(ncol);
-    const int64_t ntiles = (ncol + C - 1) / C;
+    SweepGeometry geo;
+    HIP_TRY(sweep_geometry(ncol, a.nslots, &geo));
+    const int64_t ntiles = geo.tiles;
     int rc = ensure_tiles(ntiles);
     if (rc) return rc;
+    static const int nxcd = [] {
+        const char *e = getenv("CASIM_XCDS");
+        const int v = e ? atoi(e) : kXcds;
+        return v >= 1 && v <= 64 ? v : kXcds;
+    }();
+    static const int forced_group = [] {
+        const char *e = getenv("CASIM_XCD_GROUP");
+        const int v = e ? atoi(e) : 0;
+        return v >= 1 && v <= 4096 ? v : 0;
+    }();
+    // Groups of 16 to 64 blocks (256 to 1024 columns): the largest power of
+    // two that still gives every XCD 16 groups, so that clustered cloud
+    // spreads evenly over the XCDs (measured: 32 on 65,536 columns, 64 on
+    // 1,048,576; smaller groups lose the streaming gain, larger ones the
+    // balance).
+    int group = forced_group;
+    if (!group) {
+        group = kXcdGroupMin;
+        while (group < kXcdGroupMax && geo.blocks / ((int64_t)nxcd * 16) >= 2 * group) group *= 2;
+    }
+    a.nxcd = nxcd;
+    a.xcd_group = group;
     if (!g.reserve_tiles) {
         int cus = 0;
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g.device));
         g.reserve_tiles = 12 * (cus > 0 ? cus : 1);       // one dispatch round: 3 wavefronts x 4 SIMDs per CU
     }
+    // one dispatch round of one XCD's compute units
+    const int64_t reserve = (g.reserve_tiles + nxcd - 1) / nxcd;
     static const int enabled = [] { const char *e = getenv("CASIM_TILE_ORDER"); return e ? atoi(e) : 1; }();
     const bool same = g.hist && g.hist_in0 == (const void *)s->in[0] && g.hist_ncol == ncol &&
                       g.hist_ld == s->ld && g.hist_nlev == nlev && g.hist_mode == g.c.mode &&
@@ -317,7 +344,7 @@ int plan_tiles(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, h
     a.tile_busy = g.d_busy;
     a.order = nullptr;
     if (same && enabled) {
-        HIP_TRY(launch_tile_order(g.d_busy, ntiles, g.reserve_tiles, g.d_order, st));
+        HIP_TRY(launch_tile_order(g.d_busy, geo, nxcd, group, reserve, g.d_order, st));
         a.order = g.d_order;
     }
     g.hist = true;

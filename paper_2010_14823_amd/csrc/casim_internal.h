@@ -121,6 +121,48 @@ struct SweepArgs {
     const int32_t *order;
     int32_t *tile_busy;
     int64_t ntiles;
+    int32_t nxcd, xcd_group;   // block renumbering, see virtual_block (nxcd 1: none)
+};
+
+// The hardware deals the blocks of a launch to the XCDs round-robin (block b
+// to XCD b mod nx), each XCD with its own L2.  The sweep renumbers them so
+// that each XCD runs groups of G consecutive virtual blocks: virtual blocks
+// [G (nx j + x), G (nx j + x) + G) are the j-th group of XCD x, in its
+// dispatch order.  Neighbouring tiles, whose rows share DRAM pages, then
+// stream through one L2 at about the same time, while the groups of the
+// XCDs alternate across the domain, so clustered cloud still spreads evenly
+// over the XCDs.  Blocks past the last whole round of groups keep their
+// number.  The renumbering is a bijection of [0, nb) for any nx, G >= 1.
+struct XcdMap {
+    uint32_t nb, nx, G, nbf;       // nbf: blocks in whole rounds of groups
+};
+__host__ __device__ inline XcdMap xcd_map(uint32_t nb, uint32_t nx, uint32_t G) {
+    return XcdMap{nb, nx, G, nx * G > 0 ? nb / (nx * G) * (nx * G) : 0u};
+}
+__host__ __device__ inline uint32_t virtual_block(uint32_t b, const XcdMap &m) {
+    if (m.nx <= 1 || b >= m.nbf) return b;
+    const uint32_t x = b % m.nx, i = b / m.nx;
+    return m.G * (m.nx * (i / m.G) + x) + i % m.G;
+}
+// Blocks XCD x runs, and the virtual block of the i-th of them.
+__host__ __device__ inline uint32_t xcd_blocks(uint32_t x, const XcdMap &m) {
+    const uint32_t full = m.nbf / m.nx, rest = m.nb - m.nbf;
+    return full + (rest > x ? (rest - x + m.nx - 1) / m.nx : 0u);
+}
+__host__ __device__ inline uint32_t xcd_block(uint32_t x, uint32_t i, const XcdMap &m) {
+    const uint32_t full = m.nbf / m.nx;
+    if (i < full) return m.G * (m.nx * (i / m.G) + x) + i % m.G;
+    return m.nbf + x + m.nx * (i - full);
+}
+constexpr int kXcds = 8;
+constexpr int kXcdGroupMin = 16, kXcdGroupMax = 64;   // blocks per group (16: 256 columns, any tile width)
+
+// Launch shape of the sweep: C columns per wavefront tile, wpb wavefronts
+// per block, `blocks` blocks, `lds` bytes of LDS per block.
+struct SweepGeometry {
+    int C, wpb;
+    int64_t tiles, blocks;
+    size_t lds;
 };
 
 // Point-parallel passes over (k, column) in point order p = k*ncol + c.
@@ -158,12 +200,15 @@ constexpr int kCmpState = 13;
 // Launchers (casim_sweep.hip).  `fast` selects the kernels compiled with
 // kDefaultParams.  Return the launch's hipError_t.
 hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream);
-// Columns per wavefront tile the sweep uses for ncol columns.
-int sweep_columns_per_wave(int64_t ncol);
-// Tile launch order from the previous step's per-tile activity: busy tiles
-// and most clear ones in index order, the last `reserve` clear tiles at the end.
-hipError_t launch_tile_order(const int32_t *busy, int64_t ntiles, int64_t reserve, int32_t *order,
-                             hipStream_t stream);
+// Launch shape of the sweep for ncol columns and nslots carry slots
+// (hipErrorInvalidValue when the carries do not fit the LDS).
+hipError_t sweep_geometry(int64_t ncol, int32_t nslots, SweepGeometry *geo);
+// Tile launch order from the previous step's per-tile activity, separately
+// for the wavefront positions each XCD runs (see virtual_block): busy tiles
+// and most clear ones in index order, the XCD's last `reserve` clear tiles
+// in its last positions.
+hipError_t launch_tile_order(const int32_t *busy, const SweepGeometry &geo, int32_t nxcd, int32_t group,
+                             int64_t reserve, int32_t *order, hipStream_t stream);
 hipError_t launch_apply(const SweepArgs &a, double dt, hipStream_t stream);
 hipError_t launch_math(const double *x, int64_t n, double *e, double *l, hipStream_t stream);
 hipError_t launch_points(const DevParams &P, bool fast, const PointArgs &pa, hipStream_t stream);

@@ -492,10 +492,12 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
     const int wib = threadIdx.x / kWave;
     const int g = lane / C, c = lane % C;
     double *lds = lds_all + (size_t)wib * (a.nslots + 8) * C;
-    // wavefront -> tile of C columns: the launch order derived from the
+    // wavefront -> tile of C columns: the virtual position of the wavefront
+    // (XCD groups, see virtual_block), then the launch order derived from the
     // previous step's activity, else the identity (a corrupt entry falls back
     // to the identity, so no wavefront can leave the domain)
-    const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x / kWave) + wib;
+    const uint32_t vb = virtual_block(blockIdx.x, xcd_map(gridDim.x, (uint32_t)a.nxcd, (uint32_t)a.xcd_group));
+    const int64_t wave_id = (int64_t)vb * (blockDim.x / kWave) + wib;
     int64_t tile = wave_id;
     if (a.order && wave_id < a.ntiles) {
         const int64_t o = a.order[wave_id];
@@ -894,38 +896,58 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *buf,
     return incl - v;
 }
 
-__global__ __launch_bounds__(1024) void tile_order_kernel(const int32_t *busy, int64_t n, int64_t reserve,
-                                                          int32_t *order) {
+// One block per XCD x: the tiles of the wavefront positions x runs, in its
+// dispatch order.
+struct XcdPositions {
+    XcdMap m;
+    int32_t wpb;
+    uint32_t x;
+    __device__ int64_t operator()(int64_t i) const {       // i-th position of XCD x
+        return (int64_t)xcd_block(x, (uint32_t)(i / wpb), m) * wpb + i % wpb;
+    }
+};
+
+__global__ __launch_bounds__(1024) void tile_order_kernel(const int32_t *busy, int64_t ntiles, uint32_t nb,
+                                                          int32_t wpb, int32_t nxcd, int32_t group,
+                                                          int64_t reserve, int32_t *order) {
     __shared__ int64_t buf[1024];
     __shared__ int64_t total;
     const int t = threadIdx.x;
+    const XcdPositions pos{xcd_map(nb, (uint32_t)nxcd, (uint32_t)group), wpb, blockIdx.x};
+    // positions past the last tile are the last wavefronts of the last block
+    int64_t n = (int64_t)xcd_blocks(blockIdx.x, pos.m) * wpb;
+    while (n > 0 && pos(n - 1) >= ntiles) --n;
+    if (n == 0) return;                        // the same for the whole block
     const int64_t per = (n + 1023) / 1024;
     const int64_t b = (int64_t)t * per < n ? (int64_t)t * per : n;
     const int64_t e = b + per < n ? b + per : n;
     int64_t nclear = 0;
-    for (int64_t i = b; i < e; ++i) nclear += busy[i] == 0;
-    // clear tiles after this range = all clear tiles - clear tiles up to its end
+    for (int64_t i = b; i < e; ++i) nclear += busy[pos(i)] == 0;
+    // clear tiles of the XCD after this thread's part
     const int64_t before = block_exclusive_scan(nclear, buf, &total);
     const int64_t after = total - before - nclear;
-    // reserved tiles of this range: clear, with at most `reserve` clear tiles at or after them
+    // reserved tiles of this part: clear, with at most `reserve` clear tiles at or after them
     int64_t ns = 0, suffix = after;
     for (int64_t i = e - 1; i >= b; --i)
-        if (busy[i] == 0 && ++suffix <= reserve) ++ns;
-    int64_t rank = block_exclusive_scan(ns, buf, &total);     // reserved tiles before this range
+        if (busy[pos(i)] == 0 && ++suffix <= reserve) ++ns;
+    int64_t rank = block_exclusive_scan(ns, buf, &total);     // reserved tiles before this part
     const int64_t first_reserved = n - total;
     int64_t clear_seen = 0;
     for (int64_t i = b; i < e; ++i) {
-        const bool clear = busy[i] == 0;
+        const int64_t tile = pos(i);
+        const bool clear = busy[tile] == 0;
         const bool reserved = clear && after + (nclear - clear_seen) <= reserve;
-        order[reserved ? first_reserved + rank : i - rank] = (int32_t)i;
+        order[pos(reserved ? first_reserved + rank : i - rank)] = (int32_t)tile;
         rank += reserved;
         clear_seen += clear;
     }
 }
 
-hipError_t launch_tile_order(const int32_t *busy, int64_t ntiles, int64_t reserve, int32_t *order,
-                             hipStream_t stream) {
-    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, stream, busy, ntiles, reserve, order);
+hipError_t launch_tile_order(const int32_t *busy, const SweepGeometry &geo, int32_t nxcd, int32_t group,
+                             int64_t reserve, int32_t *order, hipStream_t stream) {
+    if (nxcd < 1 || group < 1 || geo.blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tile_order_kernel, dim3((unsigned)nxcd), dim3(1024), 0, stream, busy, geo.tiles,
+                       (uint32_t)geo.blocks, geo.wpb, nxcd, group, reserve, order);
     return hipGetLastError();
 }
 
@@ -973,12 +995,10 @@ hipError_t launch_var(int var, int C, dim3 grid, dim3 block, size_t lds, hipStre
     return launch_c<MIX, VAR_GENERIC, SRC>(C, grid, block, lds, s, P, a);
 }
 
-}  // namespace
-
 // Columns per wavefront.  16-column tiles (16 x 4 levels, one 128-byte row
 // per level) measured best on the large domains; narrower tiles keep at
 // least 2048 wavefronts (two per SIMD) on small ones.
-int sweep_columns_per_wave(int64_t ncol) {
+int columns_per_wave(int64_t ncol) {
     const int forced = env_int("CASIM_COLS_PER_WAVE", 0);
     if (forced == 4 || forced == 8 || forced == 16 || forced == 32 || forced == 64) return forced;
     if (ncol / 16 >= 2048) return 16;
@@ -986,20 +1006,35 @@ int sweep_columns_per_wave(int64_t ncol) {
     return 4;
 }
 
-hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream) {
-    const int C = sweep_columns_per_wave(a.ncol);
+}  // namespace
+
+hipError_t sweep_geometry(int64_t ncol, int32_t nslots, SweepGeometry *geo) {
+    const int C = columns_per_wave(ncol);
     // narrow tiles: enough wavefronts per block to cover whole 128-byte rows,
     // so the halves of a line are fetched by one CU
     int wpb = env_int("CASIM_WAVES_PER_BLOCK", C >= 16 ? 1 : 16 / C);
     if (wpb < 1 || wpb > 4) wpb = 1;
-    const size_t per_wave = (size_t)(a.nslots + 8) * C * sizeof(double);   // carries + surface sums
+    const size_t per_wave = (size_t)(nslots + 8) * C * sizeof(double);   // carries + surface sums
     size_t lds = (size_t)wpb * per_wave;
     while (wpb > 1 && lds > 65536) { --wpb; lds = (size_t)wpb * per_wave; }
     if (lds > 65536) return hipErrorInvalidValue;
-    const int64_t waves = (a.ncol + C - 1) / C;
-    if ((a.order || a.tile_busy) && a.ntiles != waves) return hipErrorInvalidValue;
-    const int64_t blocks = (waves + wpb - 1) / wpb;
-    const dim3 grid((unsigned)blocks), block(wpb * kWave);
+    geo->C = C;
+    geo->wpb = wpb;
+    geo->tiles = (ncol + C - 1) / C;
+    geo->blocks = (geo->tiles + wpb - 1) / wpb;
+    geo->lds = lds;
+    return geo->blocks > 0x7fffffff ? hipErrorInvalidValue : hipSuccess;
+}
+
+hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream) {
+    SweepGeometry geo;
+    const hipError_t ge = sweep_geometry(a.ncol, a.nslots, &geo);
+    if (ge != hipSuccess) return ge;
+    if ((a.order || a.tile_busy) && a.ntiles != geo.tiles) return hipErrorInvalidValue;
+    if (a.nxcd < 1 || a.xcd_group < 1) return hipErrorInvalidValue;
+    const int C = geo.C;
+    const dim3 grid((unsigned)geo.blocks), block(geo.wpb * kWave);
+    const size_t lds = geo.lds;
     // the compiled-in variants need the default constants and all stages
     const int var = !(fast && a.stages == CASIM_STAGE_ALL) ? VAR_GENERIC : (a.warm ? VAR_WARM : VAR_COLD);
     if (a.mode == CASIM_MODE_FP32MIX) return launch_var<true, SRC_PLAIN>(var, C, grid, block, lds, stream, P, a);

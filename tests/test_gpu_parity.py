@@ -201,12 +201,14 @@ def test_fp32mix_tiles_agree(oracle_lib, cols_per_wave, monkeypatch):
 def test_tile_order_is_a_pure_schedule(oracle_lib, mode):
     """The second step on a state launches the tiles in the order derived
     from the first step's activity (busy tiles never in the last dispatch
-    round); every tile is still processed exactly once, so both steps give
-    bitwise the same tendencies, for the full domain and a ragged one."""
+    round) and the blocks renumbered so that each XCD runs groups of
+    neighbouring tiles; every tile is still processed exactly once, so all
+    steps give bitwise the same tendencies, for the full domain and ragged
+    ones with 16-, 8- and 4-column tiles (1, 2 and 4 wavefronts per block)."""
     import torch
     from paper_2010_14823_amd import casim
     cfg, st, dz, _ = config_state("c1")
-    for ncol in (st.shape[2], 60001):
+    for ncol in (st.shape[2], 60001, 20001, 5001):
         dev = torch.from_numpy(np.ascontiguousarray(st[:, :, :ncol])).cuda()
         outs = []
         casim.init(casim.default_constants(mode=mode))
