@@ -2,21 +2,29 @@
 //
 // The general-purpose device library routines are built for correct
 // rounding over the whole double range and cost about 40 (exp) and 90 (log)
-// vector instructions.  The step only needs a few ulp on finite, positive,
-// non-huge arguments, so these two are written from the textbook methods:
-//   exp: Cody & Waite (1980) argument reduction x = k ln2 + r, |r| <= ln2/2,
-//        with ln2 split in a high part exact in 32 bits and a low part, then
-//        the Taylor polynomial of exp(r) to degree 13 (truncation error below
-//        r^14/14! < 5e-18) and a scaling by 2^k.  About 20 instructions.
-//   log: x = m 2^e with m in [1/sqrt2, sqrt2), s = (m-1)/(m+1), and
-//        ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^21/21) (|s| <= 0.172, so
-//        the next term is below 3e-18 relative); ln x = e ln2 + ln m.  About
-//        30 instructions.  log(0) is -inf.
+// vector instructions.  The step only needs about one ulp on finite,
+// positive, non-huge arguments, so both follow Tang's table-driven methods
+// (Tang 1989 for exp, Tang 1990 for log, ACM TOMS 15(2) and 16(4)) with
+// small tables that every kernel using them copies into LDS first
+// (load_math_tables):
+//   exp: x = (64 m + j) ln2/64 + r, |r| <= ln2/128, with ln2/64 split in a
+//        part exact in 39 bits and a remainder; exp(x) = 2^m 2^(j/64)
+//        (1 + p(r)), p the Taylor polynomial of exp(r) - 1 to degree 5
+//        (truncation error below r^6/720 < 4e-17).  16 instructions.
+//   log: x = m 2^e, m in [1/2, 1), j = round(256 m) in [128, 256],
+//        c_j = 256/j rounded; ln x = e ln2 - ln c_j + log1p(m c_j - 1) with
+//        |m c_j - 1| <= 1/256 and the Taylor polynomial of log1p to
+//        degree 7 (next term below 2e-18 relative); -ln c_j is tabulated
+//        in two parts whose high part, like that of ln 2, lies on the
+//        2^-33 grid, so e ln2_hi - ln c_j,hi is exact and ln 1 is exactly
+//        0.  23 instructions.  log(0) is -inf.
 // Both are checked against the host library by the test-suite through
 // casim_debug_math.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "casim_math_tables.h"
 
 namespace casim {
 
@@ -40,57 +48,52 @@ __device__ __forceinline__ double lin_sc(double a, double c1, double c0) {
     return d;
 }
 
+// The tables in LDS (one copy per block).
+static __shared__ double s_exp2_tab[kExpTab];
+static __shared__ double s_log_tab[kLogTab][3];
+constexpr int kMathLdsBytes = (kExpTab + 3 * kLogTab) * 8;
+
+// Every kernel that calls exp64 or log64 runs this first, with all threads
+// of the block (it ends with a block barrier).
+__device__ __forceinline__ void load_math_tables() {
+    for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_exp2_tab[i] = kExp2Tab[i];
+    for (int i = threadIdx.x; i < 3 * kLogTab; i += blockDim.x) (&s_log_tab[0][0])[i] = (&kLogTabData[0][0])[i];
+    __syncthreads();
+}
+
 __device__ __forceinline__ double exp64(double x) {
-    const double log2e = 1.4426950408889634074;
-    const double ln2_hi = 6.93147180369123816490e-01;   // upper bits of ln 2
-    const double ln2_lo = 1.90821492927058770002e-10;   // ln 2 - ln2_hi
-    const double kd = __builtin_rint(x * log2e);
-    double r = __builtin_fma(-kd, ln2_hi, x);
-    r = __builtin_fma(-kd, ln2_lo, r);
-    // Horner form of sum_{n=0}^{13} r^n / n!
-    double p = lin_sc(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);   // 1/13!, 1/12!
-    p = fma_sc(p, r, 1.0 / 39916800.0);
-    p = fma_sc(p, r, 1.0 / 3628800.0);
-    p = fma_sc(p, r, 1.0 / 362880.0);
-    p = fma_sc(p, r, 1.0 / 40320.0);
-    p = fma_sc(p, r, 1.0 / 5040.0);
-    p = fma_sc(p, r, 1.0 / 720.0);
-    p = fma_sc(p, r, 1.0 / 120.0);
-    p = fma_sc(p, r, 1.0 / 24.0);
-    p = fma_sc(p, r, 1.0 / 6.0);
-    p = __builtin_fma(p, r, 0.5);
-    p = __builtin_fma(p, r, 1.0);
-    p = __builtin_fma(p, r, 1.0);
+    const double kd = __builtin_rint(x * (64.0 / 0.69314718055994530942));
     const int k = (int)kd;
-    return __builtin_ldexp(p, k);
+    double r = __builtin_fma(-kd, kLn2Hi * (1.0 / 64.0), x);   // exact product
+    r = __builtin_fma(-kd, kLn2Lo * (1.0 / 64.0), r);
+    // exp(r) - 1 = r (1 + r/2 + r^2/6 + r^3/24 + r^4/120)
+    double q = lin_sc(r, 1.0 / 120.0, 1.0 / 24.0);
+    q = fma_sc(q, r, 1.0 / 6.0);
+    q = __builtin_fma(q, r, 0.5);
+    q = __builtin_fma(q, r, 1.0);
+    const double t = s_exp2_tab[k & (kExpTab - 1)];
+    return __builtin_ldexp(__builtin_fma(t, q * r, t), k >> 6);
 }
 
 __device__ __forceinline__ double log64(double x) {
-    const double ln2_hi = 6.93147180369123816490e-01;
-    const double ln2_lo = 1.90821492927058770002e-10;
-    int e = __builtin_amdgcn_frexp_exp(x);             // x = m 2^e, m in [0.5, 1)
-    double m = __builtin_amdgcn_frexp_mant(x);
-    if (m < 0.70710678118654752440) { m *= 2.0; e -= 1; }
-    double rm = __builtin_amdgcn_rcp(m + 1.0);              // 1/(m+1), refined twice
-    rm = __builtin_fma(rm, __builtin_fma(-(m + 1.0), rm, 1.0), rm);
-    rm = __builtin_fma(rm, __builtin_fma(-(m + 1.0), rm, 1.0), rm);
-    const double s = (m - 1.0) * rm;
-    const double z = s * s;
-    // sum_{j=0}^{10} z^j / (2j+1)
-    double q = lin_sc(z, 1.0 / 21.0, 1.0 / 19.0);
-    q = fma_sc(q, z, 1.0 / 17.0);
-    q = fma_sc(q, z, 1.0 / 15.0);
-    q = fma_sc(q, z, 1.0 / 13.0);
-    q = fma_sc(q, z, 1.0 / 11.0);
-    q = fma_sc(q, z, 1.0 / 9.0);
-    q = fma_sc(q, z, 1.0 / 7.0);
-    q = fma_sc(q, z, 1.0 / 5.0);
-    q = fma_sc(q, z, 1.0 / 3.0);
-    q = __builtin_fma(q, z, 1.0);
+    const int e = __builtin_amdgcn_frexp_exp(x);           // x = m 2^e, m in [0.5, 1)
+    const double m = __builtin_amdgcn_frexp_mant(x);
+    // nearest table point; the clamp (before the conversion) keeps 0, inf
+    // and NaN inside the table
+    const int j = (int)__builtin_rint(::fmin(::fmax(m * 256.0, 128.0), 256.0));
+    const double *T = s_log_tab[j - 128];
+    const double r = __builtin_fma(m, T[0], -1.0);
+    // log1p(r) = r + r^2 (-1/2 + r/3 - r^2/4 + r^3/5 - r^4/6 + r^5/7)
+    double q = lin_sc(r, 1.0 / 7.0, -1.0 / 6.0);
+    q = fma_sc(q, r, 1.0 / 5.0);
+    q = fma_sc(q, r, -0.25);
+    q = fma_sc(q, r, 1.0 / 3.0);
+    q = __builtin_fma(q, r, -0.5);
+    const double p = __builtin_fma(r * r, q, r);
     const double ed = (double)e;
-    const double lm = 2.0 * s * q;
-    const double r = __builtin_fma(ed, ln2_hi, __builtin_fma(ed, ln2_lo, lm));
-    return x == 0.0 ? -__builtin_inf() : r;
+    const double hi = __builtin_fma(ed, kLn2Hi, T[1]);     // exact: both on the 2^-33 grid
+    const double lo = __builtin_fma(ed, kLn2Lo, T[2]) + p;
+    return x == 0.0 ? -__builtin_inf() : hi + lo;
 }
 
 // 1/x for positive, finite, normal x: the hardware reciprocal estimate

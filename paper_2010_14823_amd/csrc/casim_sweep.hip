@@ -487,6 +487,7 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
     constexpr int L = kWave / C;
     constexpr bool FAST = VAR != VAR_GENERIC;
     const DevParams &P = params<FAST>(Prt);
+    load_math_tables();
     extern __shared__ double lds_all[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wib = threadIdx.x / kWave;
@@ -700,12 +701,10 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
 // depend on scheduling); POINT_SURR computes features and gates of every
 // point where a rate can be non-zero, reserves it a slot and records the slot
 // in idx_map.
-template <bool FAST>
-__global__ __launch_bounds__(256) void point_kernel(DevParams Prt, PointArgs pa) {
-    const DevParams &P = params<FAST>(Prt);
+// One 256-point block lb of the pass (all threads of the block call it).
+__device__ __forceinline__ void point_block(const DevParams &P, const PointArgs &pa, int64_t lb, int *wave_cnt) {
     const SweepArgs &a = pa.s;
-    __shared__ int wave_cnt[4];
-    const int64_t pid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t pid = lb * 256 + threadIdx.x;
     const int64_t npts = (int64_t)a.nlev * a.ncol;
     const bool valid = pid < npts;
     const int64_t k = valid ? pid / a.ncol : 0, col = valid ? pid - k * a.ncol : 0;
@@ -755,7 +754,7 @@ __global__ __launch_bounds__(256) void point_kernel(DevParams Prt, PointArgs pa)
     if (slotted) {
         // one atomic per wavefront reserves the wave's slots; a point's slot is
         // the wave's base plus its rank among the selected lanes (mbcnt)
-        const int64_t region = blockIdx.x % kSlotRegions;
+        const int64_t region = lb % kSlotRegions;
         unsigned long long base = 0;
         if (lane == 0 && bal)
             base = atomicAdd(pa.counter + region * kCounterStride, (unsigned long long)__popcll(bal));
@@ -779,13 +778,13 @@ __global__ __launch_bounds__(256) void point_kernel(DevParams Prt, PointArgs pa)
     if (lane == 0) wave_cnt[wv] = __popcll(bal);
     __syncthreads();
     if (pa.mode == POINT_COUNT) {
-        if (threadIdx.x == 0) pa.block_counts[blockIdx.x] = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+        if (threadIdx.x == 0) pa.block_counts[lb] = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
         return;
     }
     int before = 0;
     for (int j = 0; j < wv; ++j) before += wave_cnt[j];
     if (sel) {
-        const int64_t pos = pa.block_offsets[blockIdx.x] + before + in_wave;
+        const int64_t pos = pa.block_offsets[lb] + before + in_wave;
         if (pos < pa.max_out) {
 #pragma unroll
             for (int j = 0; j < 12; ++j) {
@@ -797,6 +796,20 @@ __global__ __launch_bounds__(256) void point_kernel(DevParams Prt, PointArgs pa)
     }
 }
 
+// The blocks of the pass loop over the 256-point blocks, so that the math
+// tables are copied into LDS once per resident block, not once per 256 points.
+template <bool FAST>
+__global__ __launch_bounds__(256) void point_kernel(DevParams Prt, PointArgs pa) {
+    const DevParams &P = params<FAST>(Prt);
+    load_math_tables();
+    __shared__ int wave_cnt[4];
+    const int64_t nlb = ((int64_t)pa.s.nlev * pa.s.ncol + 255) / 256;
+    for (int64_t lb = blockIdx.x; lb < nlb; lb += gridDim.x) {
+        point_block(P, pa, lb, wave_cnt);
+        __syncthreads();                       // wave_cnt is reused
+    }
+}
+
 // The 12 binary64 rates of compacted points, one point per lane with every
 // lane of a wavefront busy (grid-stride over the slots the point pass filled).
 // ln rho and (rho_0/rho)^1/2 are formed exactly as in the sweep.
@@ -805,6 +818,7 @@ __global__ __launch_bounds__(256) void dense_rates_kernel(DevParams Prt, const d
                                                           const unsigned long long *counters, int64_t rcap,
                                                           double *out, int warm_i) {
     const DevParams &P = params<FAST>(Prt);
+    load_math_tables();
     const bool warm = warm_i != 0;
     // block r works through region r (one block per region)
     const int64_t r = blockIdx.x;
@@ -1016,8 +1030,10 @@ hipError_t sweep_geometry(int64_t ncol, int32_t nslots, SweepGeometry *geo) {
     if (wpb < 1 || wpb > 4) wpb = 1;
     const size_t per_wave = (size_t)(nslots + 8) * C * sizeof(double);   // carries + surface sums
     size_t lds = (size_t)wpb * per_wave;
-    while (wpb > 1 && lds > 65536) { --wpb; lds = (size_t)wpb * per_wave; }
-    if (lds > 65536) return hipErrorInvalidValue;
+    // 64 KiB per block, the math tables included
+    const size_t lds_max = 65536 - kMathLdsBytes;
+    while (wpb > 1 && lds > lds_max) { --wpb; lds = (size_t)wpb * per_wave; }
+    if (lds > lds_max) return hipErrorInvalidValue;
     geo->C = C;
     geo->wpb = wpb;
     geo->tiles = (ncol + C - 1) / C;
@@ -1046,7 +1062,9 @@ hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipSt
 
 hipError_t launch_points(const DevParams &P, bool fast, const PointArgs &pa, hipStream_t stream) {
     const int64_t npts = (int64_t)pa.s.nlev * pa.s.ncol;
-    const int64_t blocks = (npts + 255) / 256;
+    // 32 blocks of 256 threads per compute unit of an MI355X, at most
+    const int64_t blocks = ::min((npts + 255) / 256, (int64_t)8192);
+    if (blocks == 0) return hipSuccess;
     if (fast) hipLaunchKernelGGL(point_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, stream, P, pa);
     else hipLaunchKernelGGL(point_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, stream, P, pa);
     return hipGetLastError();
@@ -1058,6 +1076,7 @@ hipError_t launch_scan(const int64_t *counts, int64_t n, int64_t *offsets, int64
 }
 
 __global__ __launch_bounds__(256) void math_kernel(const double *x, int64_t n, double *e, double *l) {
+    load_math_tables();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (e) e[i] = exp64(x[i]);
