@@ -72,7 +72,7 @@ def recorded_traffic(cfg_name, mode):
     return float(rec["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(st, dz, dt, budget_s=12.0):
+def cpu_baseline(st, dz, dt, budget_s=10.0):
     import oracle
     nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     nthreads = min(nthreads, 16)
@@ -84,13 +84,14 @@ def cpu_baseline(st, dz, dt, budget_s=12.0):
         t0 = time.perf_counter()
         oracle.step(st, dz, dt, nthreads=nthreads)
         times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start > budget_s or len(times) >= 3:
+        # about 10 s of CPU work, at least 3 steps
+        if (time.perf_counter() - t_start > budget_s and len(times) >= 3) or len(times) >= 500:
             break
     t = float(np.median(times))
     pts = st.shape[1] * st.shape[2]
     return {"value": pts / t, "unit": "grid-point updates/s", "cores": nthreads, "kind": "oracle",
-            "sample": "%d columns x %d levels of the same workload, median of %d full steps (%.2f s each)"
-                      % (st.shape[2], st.shape[1], len(times), t)}
+            "sample": "%d columns x %d levels of the same workload, median of %d full steps "
+                      "(%.3f s each, %.1f s in all)" % (st.shape[2], st.shape[1], len(times), t, sum(times))}
 
 
 def compare_with_plain(torch, casim, dev, dz, cfg, tend, sfc, mode, warm=0):
