@@ -89,9 +89,26 @@ def cpu_baseline(st, dz, dt, budget_s=10.0):
             break
     t = float(np.median(times))
     pts = st.shape[1] * st.shape[2]
+    # one thread on the first 1/16 of the columns (about 2-3 s)
+    sub = np.ascontiguousarray(st[:, :, :max(64, st.shape[2] // 16)])
+    t1 = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.step(sub, dz, dt, nthreads=1)
+        t1.append(time.perf_counter() - t0)
+    t1m = float(np.median(t1))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": pts / t, "unit": "grid-point updates/s", "cores": nthreads, "kind": "oracle",
             "sample": "%d columns x %d levels of the same workload, median of %d full steps "
-                      "(%.3f s each, %.1f s in all)" % (st.shape[2], st.shape[1], len(times), t, sum(times))}
+                      "(%.3f s each, %.1f s in all)" % (st.shape[2], st.shape[1], len(times), t, sum(times)),
+            "single_core": {"value": sub.shape[1] * sub.shape[2] / t1m, "cores": 1,
+                            "sample": "first %d columns, median of 3 steps (%.2f s each)" % (sub.shape[2], t1m)},
+            "host": {"cpu": model, "nproc": os.cpu_count()}}
 
 
 def compare_with_plain(torch, casim, dev, dz, cfg, tend, sfc, mode, warm=0):
