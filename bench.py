@@ -193,8 +193,8 @@ def host_pipeline(torch, casim, st, dz, dt, nblocks=0, reps=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--config", default="c1")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32mix", "surrogate", "fp64compact"])
     ap.add_argument("--checkpoint", default=None, help="surrogate checkpoint (casim_mlp_save blob)")
