@@ -5,8 +5,12 @@
 // a tile of C columns x L = 64/C consecutive levels (lane = g*C + c: column c
 // of the wave's column block, level group g, g = 0 the top of the tile), and
 // walks its columns from the top level down in chunks of L levels.  C = 64
-// is the one-column-per-lane mapping; C = 16 or 32 gives domains with few
-// columns four or two times as many wavefronts.  Per chunk a wavefront
+// would be the paper's one-column-per-lane mapping; C = 16 (one 128-byte row
+// of every field per level) is used on large domains and 8 or 4 on small
+// ones, for enough wavefronts.  Which tile a wavefront takes is a pure
+// schedule: blocks are renumbered so that each XCD streams groups of
+// neighbouring tiles, and tiles that were busy in the previous step are kept
+// out of the last dispatch round (tile_order_kernel).  Per chunk a wavefront
 //   1. reads the 8 fields that decide whether anything can happen at a point
 //      (T, p, q_v and the five condensate masses);
 //   2. votes: when no point of the chunk has condensate or supersaturation
