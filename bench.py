@@ -284,7 +284,8 @@ def main():
                    "configuration": "warm" if args.warm else "cold"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "sweep_kernel" if args.mode in ("fp64", "fp32mix")
+                     "kernel": ("sweep_kernel (HIP events around the step: the ~7 us tile-order kernel "
+                                "that precedes it is included)") if args.mode in ("fp64", "fp32mix")
                                else "whole step: point pass, rate kernel, sweep",
                      "kernel_ms": kern_ms, "algorithmic_bytes": alg},
         "status": status,
