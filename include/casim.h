@@ -173,7 +173,10 @@ int casim_init(const casim_constants *c, const casim_thresholds *t);
  * (Sec. III-B: one offloaded pass over all columns writing a source term per
  * field).  Errors: ENOINIT, EINVAL (NULL pointer, ncol < 0, nlev outside
  * 1..CASIM_MAX_NLEV, ld < ncol, dt not finite or <= 0, dz not finite or
- * <= 0), ENOSURROGATE, ECAPACITY, EHIP.  ncol == 0 is a no-op. */
+ * <= 0), ENOSURROGATE, ECAPACITY (the sedimentation substeps need more than
+ * 64 carry slots: 2 x the sum of the four substep counts of casim_nsub,
+ * e.g. 512 thin levels at dt = 2 s), EHIP.  All checks happen before
+ * anything is enqueued.  ncol == 0 is a no-op. */
 int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream);
 
 /* Parent-model helper for multi-step runs: X += dt * tend for the 12
