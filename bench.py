@@ -206,9 +206,10 @@ def main():
     ap.add_argument("--host-pipeline", action="store_true",
                     help="also time casim_step_host (state in page-locked host memory, both PCIe "
                          "directions included) alone and overlapped with a host workload")
-    ap.add_argument("--with-copy", action="store_true",
-                    help="also time a plain device-to-device copy of 2 GiB (bandwidth reference "
-                         "and scale for the HBM byte counters)")
+    ap.add_argument("--no-copy", action="store_true",
+                    help="skip the plain device-to-device copy of 2 GiB that is timed after the step "
+                         "(the achievable-bandwidth reference and the scale for the HBM byte counters)")
+    ap.add_argument("--with-copy", action="store_true", help="(the default; kept for older command lines)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the column step needs no exchange between GPUs "
@@ -297,8 +298,9 @@ def main():
     if args.compare and args.mode != "fp64":
         line["error_vs_fp64_plain"] = compare_with_plain(torch, casim, dev, dz, cfg, tend, sfc, mode,
                                                            1 if args.warm else 0)
-    if args.with_copy:
+    if not args.no_copy:
         line["copy_probe"] = copy_probe(torch)
+        line["roofline"]["frac_of_copy"] = achieved / line["copy_probe"]["GBps"]
     if args.host_pipeline:
         line["host_pipeline"] = host_pipeline(torch, casim, st, dz, cfg.dt)
     if not args.no_cpu:
