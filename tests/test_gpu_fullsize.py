@@ -23,8 +23,10 @@ def _sample(ncol, rng):
     return np.unique(idx)
 
 
-@pytest.mark.parametrize("key", ["c3", "c2"])
-def test_full_domain_sampled_columns(oracle_lib, key):
+@pytest.mark.parametrize("key,mode", [("c3", 0), ("c2", 0), ("c3", 1)])
+def test_full_domain_sampled_columns(oracle_lib, key, mode):
+    """mode 0: binary64, bound 1e-12; mode 1: FP32-mixed (rates and fall
+    speeds in float32), bound 1e-3 as for its ten-step test."""
     import torch
     from paper_2010_14823_amd import casim
     cfg = synth.CONFIGS[key]
@@ -35,7 +37,7 @@ def test_full_domain_sampled_columns(oracle_lib, key):
     dev = torch.from_numpy(st).cuda()
     tend = torch.full((12, cfg.nlev, ncol), -7.0, dtype=torch.float64, device="cuda")
     sfc = torch.full((8, ncol), -7.0, dtype=torch.float64, device="cuda")
-    casim.init()
+    casim.init(casim.default_constants(mode=mode))
     casim.status()
     idx = _sample(ncol, np.random.default_rng(11))
     it = torch.from_numpy(idx).cuda()
@@ -51,8 +53,9 @@ def test_full_domain_sampled_columns(oracle_lib, key):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     to, so = oracle_lib.step(np.ascontiguousarray(st[:, :, idx]), dz, cfg.dt)
     errs = field_errors(outs[1][0], outs[1][1], to, so)
-    print(key, "sampled columns", idx.size, {k: float("%.3g" % v) for k, v in errs.items()}, status, flush=True)
-    bad = {k: v for k, v in errs.items() if not v <= TOL}
+    print(key, "mode", mode, "sampled columns", idx.size, {k: float("%.3g" % v) for k, v in errs.items()}, status,
+          flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= (TOL if mode == 0 else 1e-3)}
     assert not bad, bad
     assert status["nonfinite"] == 0
 
