@@ -232,7 +232,13 @@ typedef struct casim_mlp_stats {
     float x_mean[12], x_std[12];   /* features                               */
     float x_min[12], x_max[12];    /* training range of every feature        */
     float y_mean[12], y_std[12];   /* scaled targets over open gates         */
-    float cov_inv[144];            /* inverse covariance of standardised features */
+    float whiten[144];             /* W, row-major and lower-triangular, with
+                                      W^T W = (C + 1e-9 I)^-1 for the covariance C of
+                                      the standardised features (W = L^-1, L L^T the
+                                      Cholesky factorisation): the squared
+                                      Mahalanobis distance is |W z|^2, a sum of
+                                      squares that float32 evaluates without the
+                                      cancellation of z^T C^-1 z */
     float maha_q999;               /* 99.9th percentile of the squared Mahalanobis distance */
     float reserved[3];
 } casim_mlp_stats;
@@ -302,6 +308,20 @@ int casim_surrogate_load(void);
  * or the training 99.9th percentile when that is 0). */
 int casim_surrogate_infer(const float *feat, const uint16_t *gates, int64_t n, float *rates,
                           uint8_t *fallback, void *stream);
+
+/* The rates a CASIM_MODE_SURROGATE step would take from the network, per
+ * point, through the step's own path (point pass -> slot -> network), for
+ * inspection and testing: rates is a device array [12][nlev][ld] of float32
+ * (kg/kg/s, gates and sign rules applied), flags a device array [nlev][ld]
+ * of uint8: 0 = the network's rates (inside the trust region), 1 = outside
+ * the trust region (the step uses the plain rates), 2 = no rate gate open
+ * (rates 0).  The step additionally falls back where the limiter would scale
+ * a category by less than sur_f_min; that test happens in the step itself.
+ * Only the 14 input pointers, dz and ld of *s are used.  Works in any mode
+ * of the current context.  Errors: ENOINIT, EINVAL (as casim_step),
+ * ENOSURROGATE, ECAPACITY, EHIP. */
+int casim_surrogate_rates(const casim_state *s, int64_t ncol, int32_t nlev, double dt, float *rates,
+                          uint8_t *flags, void *stream);
 
 /* ======================================================================
  * Host-resident state: copy in, step, copy out.

@@ -73,6 +73,8 @@ def lib():
         L.oracle_point_process.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, dp, dp]
         L.oracle_point_process.restype = None
         L.oracle_nsub.restype = None
+        L.oracle_point_apply.argtypes = [dp, dp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, dp]
+        L.oracle_point_apply.restype = None
         _lib = L
     return _lib
 
@@ -149,3 +151,12 @@ def point_process(in14, warm=False, newton_iters=5):
     r = np.zeros(12)
     lib().oracle_point_process(_dptr(v), 1 if warm else 0, newton_iters, _dptr(st), _dptr(r))
     return st, r
+
+
+def point_apply(in14, rates12, dt, warm=False, newton_iters=5):
+    """Tendencies (12,) of one point whose S4 rates are replaced by rates12."""
+    v = np.ascontiguousarray(in14, dtype=np.float64)
+    r = np.ascontiguousarray(rates12, dtype=np.float64)
+    out = np.zeros(12)
+    lib().oracle_point_apply(_dptr(v), _dptr(r), float(dt), 1 if warm else 0, newton_iters, _dptr(out))
+    return out

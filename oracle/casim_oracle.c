@@ -497,6 +497,35 @@ void oracle_point_process(const double in14[14], int32_t warm, int32_t newton_it
     oracle_point_rates(w.T, p, rho, w.q, w.n, warm, rates);
 }
 
+/* S1-S3 on one point, then S5 with the supplied 12 rates in place of the
+ * S4 rates (how a learned surrogate's rates enter the step); tend12 receives
+ * the point's 12 tendencies (increment / dt) in the tendency order. */
+void oracle_point_apply(const double in14[14], const double rates[12], double dt, int32_t warm,
+                        int32_t newton_iters, double tend12[12])
+{
+    pstate w; pdelta d;
+    memset(&w, 0, sizeof w); memset(&d, 0, sizeof d);
+    double p = in14[1], rho = in14[2];
+    w.T = in14[0];
+    w.q[V] = in14[3];
+    w.q[C] = in14[4]; w.n[C] = in14[5];
+    w.q[R] = in14[6]; w.n[R] = in14[7];
+    w.q[I] = in14[8]; w.n[I] = in14[9];
+    w.q[S] = in14[10]; w.n[S] = in14[11];
+    w.q[G] = in14[12]; w.n[G] = in14[13];
+    s1_cleanup(&w, &d, warm);
+    if (!warm) s2_phase(&w, &d, p, rho);
+    int bad;
+    s3_satadj(&w, &d, p, newton_iters, &bad);
+    s5_apply(&w, &d, rates, dt);
+    tend12[0] = d.T / dt; tend12[1] = d.q[V] / dt;
+    tend12[2] = d.q[C] / dt; tend12[3] = d.n[C] / dt;
+    tend12[4] = d.q[R] / dt; tend12[5] = d.n[R] / dt;
+    tend12[6] = d.q[I] / dt; tend12[7] = d.n[I] / dt;
+    tend12[8] = d.q[S] / dt; tend12[9] = d.n[S] / dt;
+    tend12[10] = d.q[G] / dt; tend12[11] = d.n[G] / dt;
+}
+
 /* column c: S1-S5 at every level (pointwise), then S6 over the column. */
 static int64_t column(const double *const in[14], const double *dz, int64_t col, int64_t ld,
                       int nlev, double dt, double *const tend[12], double *const sfc[8],

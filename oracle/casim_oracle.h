@@ -75,6 +75,12 @@ int oracle_saturation_adjust(double *T, double p, double *qv, double *qc,
 void oracle_point_process(const double in14[14], int32_t warm, int32_t newton_iters,
                           double state12[12], double rates[12]);
 
+/* Clean-up, phase changes and saturation adjustment of one point, then the
+ * limiter and apply step with the supplied 12 rates (a surrogate's rates)
+ * instead of the point's own; tend12 receives its 12 tendencies. */
+void oracle_point_apply(const double in14[14], const double rates[12], double dt, int32_t warm,
+                        int32_t newton_iters, double tend12[12]);
+
 /* Number of sedimentation substeps per category r, i, s, g. */
 void oracle_nsub(const double *dz, int32_t nlev, double dt, int32_t nsub[4]);
 

@@ -75,7 +75,7 @@ FEATURE_NAMES = ("lnT", "lnp", "lnrho", "lnqv", "lnqc", "lnnc", "lnqr", "lnnr", 
 
 class MlpStats(ctypes.Structure):
     _fields_ = [("x_mean", _f12), ("x_std", _f12), ("x_min", _f12), ("x_max", _f12),
-                ("y_mean", _f12), ("y_std", _f12), ("cov_inv", ctypes.c_float * 144),
+                ("y_mean", _f12), ("y_std", _f12), ("whiten", ctypes.c_float * 144),
                 ("maha_q999", ctypes.c_float), ("reserved", ctypes.c_float * 3)]
 
 
@@ -128,6 +128,7 @@ def lib():
             "casim_mlp_load": [vp, ctypes.c_size_t],
             "casim_surrogate_load": [],
             "casim_surrogate_infer": [vp, vp, i64, vp, vp, vp],
+            "casim_surrogate_rates": [ctypes.POINTER(State), i64, i32, dbl, vp, vp, vp],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -190,6 +191,16 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _dz_array(dz, nlev: int):
+    """dz as a contiguous float64 host array of exactly nlev entries (the
+    library reads nlev values through the pointer)."""
+    import numpy as np
+    dzh = np.ascontiguousarray(dz, dtype=np.float64)
+    if dzh.shape != (int(nlev),):
+        raise ValueError("dz must hold exactly nlev = %d layer thicknesses, got shape %s" % (nlev, dzh.shape))
+    return dzh
+
+
 def make_state(state, dz, tend, sfc, ld: int | None = None) -> State:
     """Build a casim_state from device tensors.
 
@@ -204,7 +215,7 @@ def make_state(state, dz, tend, sfc, ld: int | None = None) -> State:
         st.tend[f] = tend[f].data_ptr()
     for f in range(NSFC):
         st.sfc[f] = sfc[f].data_ptr()
-    dzh = np.ascontiguousarray(dz, dtype=np.float64)
+    dzh = _dz_array(dz, state.shape[1])
     st._dz_keep = dzh
     st.dz = dzh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     st.ld = int(ld if ld is not None else state.shape[-1])
@@ -253,6 +264,8 @@ def status(stream=None) -> dict:
 def nsub(dz, dt: float):
     import numpy as np
     dzh = np.ascontiguousarray(dz, dtype=np.float64)
+    if dzh.ndim != 1 or dzh.size < 1:
+        raise ValueError("dz must be a 1-D sequence of layer thicknesses")
     out = (ctypes.c_int32 * 4)()
     _check(lib().casim_nsub(dzh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(dzh),
                             float(dt), out), "casim_nsub")
@@ -360,6 +373,23 @@ def surrogate_infer(feat, gates, n, rates, fallback, stream=None):
                                        _stream_handle(stream)), "casim_surrogate_infer")
 
 
+def surrogate_rates(state, dz, dt, rates, flags, ncol=None, stream=None):
+    """casim_surrogate_rates: per-point network rates (12, nlev, ld) float32 and
+    trust-region flags (nlev, ld) uint8 of a surrogate step on ``state``."""
+    import torch
+    nlev, ld = state.shape[1], state.shape[2]
+    ncol = ld if ncol is None else int(ncol)
+    if not (rates.is_cuda and rates.dtype == torch.float32 and rates.is_contiguous()
+            and tuple(rates.shape) == (12, nlev, ld)):
+        raise ValueError("rates must be a contiguous float32 cuda tensor (12, nlev, ld)")
+    if not (flags.is_cuda and flags.dtype == torch.uint8 and flags.is_contiguous()
+            and tuple(flags.shape) == (nlev, ld)):
+        raise ValueError("flags must be a contiguous uint8 cuda tensor (nlev, ld)")
+    st = make_state(state, dz, rates, rates, ld)
+    _check(lib().casim_surrogate_rates(ctypes.byref(st), ncol, nlev, float(dt), _p(rates), _p(flags),
+                                       _stream_handle(stream)), "casim_surrogate_rates")
+
+
 class HostArray:
     """Page-locked host memory from casim_host_alloc, viewed as a float64 numpy
     array of the given shape; freed with ``free()`` (or when collected)."""
@@ -408,7 +438,7 @@ def step_host(state, dz, dt: float, tend, sfc, ncol: int | None = None, nblocks:
         hs.tend[f] = tend[f].ctypes.data
     for f in range(NSFC):
         hs.sfc[f] = sfc[f].ctypes.data
-    dzh = np.ascontiguousarray(dz, dtype=np.float64)
+    dzh = _dz_array(dz, nlev)
     hs.dz = dzh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     hs.ld = ld
     _check(lib().casim_step_host(ctypes.byref(hs), ncol, nlev, float(dt), int(nblocks), _stream_handle(stream)),

@@ -357,6 +357,28 @@ int plan_tiles(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, h
     return CASIM_OK;
 }
 
+// The surrogate step's rate path: features and gates of every point that
+// can react go to a slot (point pass), the network turns each slot into 12
+// rates and a trust-region flag.  Leaves the point -> slot map in d_idx.
+int surrogate_front(const SweepArgs &a, hipStream_t st) {
+    const int64_t npts = (int64_t)a.nlev * a.ncol;
+    int rc = ensure_sur(npts);
+    if (rc) return rc;
+    HIP_TRY(launch_zero_u64(g.d_count, (int64_t)kSlotRegions * kCounterStride, st));
+    PointArgs pa{};
+    pa.s = a;
+    pa.mode = POINT_SURR;
+    pa.feat = g.d_feat;
+    pa.gates = g.d_gates;
+    pa.idx_map = g.d_idx;
+    pa.counter = g.d_count;
+    pa.rcap = region_cap(npts);
+    HIP_TRY(launch_points(g.P, g.fast, pa, st));
+    HIP_TRY(launch_surrogate_infer(surrogate_dev((float)g.t.sur_range_margin, (float)g.t.sur_maha_max), g.d_feat,
+                                   g.d_gates, npts, g.d_count, pa.rcap, g.d_rates, g.d_fb, st));
+    return CASIM_OK;
+}
+
 int fill_args(const casim_state *s, int64_t ncol, int32_t nlev, double dt, SweepArgs &a) {
     for (int f = 0; f < CASIM_NIN; ++f) a.in[f] = s->in[f];
     for (int f = 0; f < CASIM_NTEND; ++f) a.tend[f] = s->tend[f];
@@ -463,21 +485,7 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     if (g.c.mode == CASIM_MODE_SURROGATE) {
-        // features and gates of every point that can react -> network -> sweep
-        const int64_t npts = (int64_t)nlev * ncol;
-        if ((rc = ensure_sur(npts))) return rc;
-        HIP_TRY(launch_zero_u64(g.d_count, (int64_t)kSlotRegions * kCounterStride, st));
-        PointArgs pa{};
-        pa.s = a;
-        pa.mode = POINT_SURR;
-        pa.feat = g.d_feat;
-        pa.gates = g.d_gates;
-        pa.idx_map = g.d_idx;
-        pa.counter = g.d_count;
-        pa.rcap = region_cap(npts);
-        HIP_TRY(launch_points(g.P, g.fast, pa, st));
-        HIP_TRY(launch_surrogate_infer(surrogate_dev((float)g.t.sur_range_margin, (float)g.t.sur_maha_max),
-                                       g.d_feat, g.d_gates, npts, g.d_count, pa.rcap, g.d_rates, g.d_fb, st));
+        if ((rc = surrogate_front(a, st))) return rc;
         a.sur_idx = g.d_idx;
         a.sur_rates = g.d_rates;
         a.sur_fallback = g.d_fb;
@@ -528,6 +536,17 @@ int casim_step_host(const casim_host_state *hs, int64_t ncol, int32_t nlev, doub
     int64_t bw = (ncol + nblocks - 1) / nblocks;
     bw = (bw + 63) / 64 * 64;
     const int64_t nb = (ncol + bw - 1) / bw;
+    // the checks casim_step makes on every block, made once before anything
+    // is enqueued, so that a rejected call leaves no copy behind
+    {
+        int32_t ns[4];
+        nsub_of(g.c, hs->dz, nlev, dt, ns);
+        if (2 * (ns[0] + ns[1] + ns[2] + ns[3]) > kMaxCarrySlots) return CASIM_ECAPACITY;
+        if (g.c.mode == CASIM_MODE_SURROGATE && !surrogate_ready()) return CASIM_ENOSURROGATE;
+        if ((g.c.mode == CASIM_MODE_SURROGATE || g.c.mode == CASIM_MODE_FP64_COMPACT) &&
+            kSlotRegions * region_cap((int64_t)nlev * bw) > INT32_MAX)
+            return CASIM_ECAPACITY;
+    }
     int rc = pipe_create();
     if (rc) return rc;
     if ((rc = ensure_pipe(bw, nlev))) return rc;
@@ -619,6 +638,36 @@ int casim_rates_dump(const casim_state *s, int64_t ncol, int32_t nlev, double dt
     HIP_TRY(hipStreamSynchronize(st));
     *n_written = total < max_samples ? total : max_samples;
     if (n_selected) *n_selected = total;
+    return CASIM_OK;
+}
+
+int casim_surrogate_rates(const casim_state *s, int64_t ncol, int32_t nlev, double dt, float *rates,
+                          uint8_t *flags, void *stream) {
+    if (!g.init) return CASIM_ENOINIT;
+    if (!s || !rates || !flags) return CASIM_EINVAL;
+    if (ncol < 0 || nlev < 1 || nlev > CASIM_MAX_NLEV || s->ld < ncol || !isfinite(dt) || !(dt > 0.0))
+        return CASIM_EINVAL;
+    if (ncol == 0) return CASIM_OK;
+    for (int f = 0; f < CASIM_NIN; ++f)
+        if (!s->in[f]) return CASIM_EINVAL;
+    if ((int64_t)nlev * s->ld > (int64_t)1 << 40) return CASIM_EINVAL;
+    if (!surrogate_ready()) return CASIM_ENOSURROGATE;
+    if (kSlotRegions * region_cap((int64_t)nlev * ncol) > INT32_MAX) return CASIM_ECAPACITY;
+    SweepArgs a{};
+    for (int f = 0; f < CASIM_NIN; ++f) a.in[f] = s->in[f];
+    a.ld = s->ld;
+    a.ncol = ncol;
+    a.nlev = nlev;
+    a.dt = dt;
+    a.status = g.d_status;
+    a.stages = g.c.stages;
+    a.warm = g.c.warm ? 1 : 0;
+    a.newton_iters = g.t.newton_iters;
+    a.mode = g.c.mode;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = surrogate_front(a, st);
+    if (rc) return rc;
+    HIP_TRY(launch_slot_scatter(g.d_idx, ncol, nlev, s->ld, g.d_rates, g.d_fb, rates, flags, st));
     return CASIM_OK;
 }
 

@@ -278,10 +278,10 @@ __global__ __launch_bounds__(256) void stats_cov(const float *feat, int64_t n, c
     }
 }
 
-// Histogram of log10 of the squared Mahalanobis distance (4096 bins over
-// [-6, 6)), integer counts, for the 99.9th percentile.
+// Histogram of log10 of the squared Mahalanobis distance |W z|^2 (4096 bins
+// over [-6, 6)), integer counts, for the 99.9th percentile.
 __global__ __launch_bounds__(256) void stats_maha_hist(const float *feat, int64_t n, const float *mean,
-                                                       const float *sd, const float *cinv,
+                                                       const float *sd, const float *whiten,
                                                        unsigned long long *hist) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -293,8 +293,8 @@ __global__ __launch_bounds__(256) void stats_maha_hist(const float *feat, int64_
     for (int a = 0; a < 12; ++a) {
         float t = 0.0f;
 #pragma unroll
-        for (int b = 0; b < 12; ++b) t = fmaf(cinv[a * 12 + b], z[b], t);
-        d2 = fmaf(z[a], t, d2);
+        for (int b = 0; b <= a; ++b) t = fmaf(whiten[a * 12 + b], z[b], t);
+        d2 = fmaf(t, t, d2);
     }
     const double l = log10(fmax((double)d2, 1e-6));
     int bin = (int)floor((l + 6.0) / 12.0 * 4096.0);
@@ -553,27 +553,29 @@ int casim_mlp_fit_stats(const float *feat, const float *rates, const uint16_t *g
     double cov[144];
     MLP_TRY(hipMemcpyAsync(cov, d_cov, sizeof cov, hipMemcpyDeviceToHost, s));
     MLP_TRY(hipStreamSynchronize(s));
-    // inverse by Gauss-Jordan elimination with partial pivoting (12 x 12, host)
-    double a[12][24];
+    // Cholesky factor L of C + 1e-9 I and W = L^-1 (12 x 12, host, binary64)
+    double L[12][12] = {}, Wd[12][12] = {};
     for (int i = 0; i < 12; ++i)
-        for (int j = 0; j < 24; ++j) a[i][j] = j < 12 ? cov[i * 12 + j] + (i == j ? 1e-9 : 0.0) : (j - 12 == i);
-    for (int c = 0; c < 12; ++c) {
-        int piv = c;
-        for (int r = c + 1; r < 12; ++r)
-            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
-        for (int j = 0; j < 24; ++j) { double t = a[c][j]; a[c][j] = a[piv][j]; a[piv][j] = t; }
-        const double d = a[c][c];
-        if (fabs(d) < 1e-300) return CASIM_EINVAL;
-        for (int j = 0; j < 24; ++j) a[c][j] /= d;
-        for (int r = 0; r < 12; ++r) {
-            if (r == c) continue;
-            const double f = a[r][c];
-            for (int j = 0; j < 24; ++j) a[r][j] -= f * a[c][j];
+        for (int j = 0; j <= i; ++j) {
+            double v = cov[i * 12 + j] + (i == j ? 1e-9 : 0.0);
+            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(v > 0.0)) return CASIM_EINVAL;
+                L[i][i] = sqrt(v);
+            } else {
+                L[i][j] = v / L[j][j];
+            }
+        }
+    for (int j = 0; j < 12; ++j) {          // forward substitution, column j of L^-1
+        for (int i = j; i < 12; ++i) {
+            double v = i == j ? 1.0 : 0.0;
+            for (int k = j; k < i; ++k) v -= L[i][k] * Wd[k][j];
+            Wd[i][j] = v / L[i][i];
         }
     }
     for (int i = 0; i < 12; ++i)
-        for (int j = 0; j < 12; ++j) st.cov_inv[i * 12 + j] = (float)a[i][j + 12];
-    MLP_TRY(hipMemcpyAsync(d_cinv, st.cov_inv, sizeof st.cov_inv, hipMemcpyHostToDevice, s));
+        for (int j = 0; j < 12; ++j) st.whiten[i * 12 + j] = (float)Wd[i][j];
+    MLP_TRY(hipMemcpyAsync(d_cinv, st.whiten, sizeof st.whiten, hipMemcpyHostToDevice, s));
     MLP_TRY(hipMemsetAsync(d_hist, 0, 4096 * sizeof(unsigned long long), s));
     hipLaunchKernelGGL(stats_maha_hist, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, feat, n, d_mean, d_sd,
                        d_cinv, d_hist);

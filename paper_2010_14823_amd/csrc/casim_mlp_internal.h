@@ -48,6 +48,11 @@ hipError_t launch_surrogate_infer(const SurrogateDev &S, const float *feat, cons
                                   const unsigned long long *counters, int64_t rcap, float *rates,
                                   uint8_t *fallback, hipStream_t stream);
 
+// Scatter slotted rates and trust-region flags back to point order.
+hipError_t launch_slot_scatter(const int32_t *idx_map, int64_t ncol, int64_t nlev, int64_t ld,
+                               const float *slot_rates, const uint8_t *slot_fb, float *rates_out, uint8_t *flags,
+                               hipStream_t stream);
+
 }  // namespace casim
 
 // Thresholds of the current context (nullptr before casim_init).

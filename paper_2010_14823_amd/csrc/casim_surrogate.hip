@@ -20,8 +20,8 @@
 // LDS holds only the weights, biases and feature statistics, and a block runs
 // 8 wavefronts (2 per SIMD).  Per point the kernel also standardises the
 // features, checks them against the training range and computes the squared
-// Mahalanobis distance (rows split over the 4 lanes of a point, summed with
-// two cross-lane exchanges), and after the last layer undoes the target
+// Mahalanobis distance |W z|^2 (rows split over the 4 lanes of a point,
+// summed with two cross-lane exchanges), and after the last layer undoes the target
 // scaling (rate = 1e-12 sinh(y)), applies the gates and the sign/positivity
 // rules.
 #include <math.h>
@@ -48,8 +48,8 @@ constexpr int kWElems = kW4 + 16 * kRowH;               // 42,112 bfloat16 = 84,
 constexpr int kBias = 128 * 3 + 16;
 constexpr int kInferWaves = 8;                          // two wavefronts per SIMD
 // LDS: weights, biases, then per feature j: mean, 1/std, lower and upper
-// range bound; per output j: target mean and std; the 12 x 12 inverse
-// covariance; the Mahalanobis limit.
+// bound of the standardised range; per output j: target mean and std; the
+// 12 x 12 whitening factor of the feature covariance; the Mahalanobis limit.
 constexpr int kStatF = 12 * 4 + 12 * 2 + 144 + 4;
 constexpr size_t kInferLds = (size_t)kWElems * 2 + (size_t)(kBias + kStatF) * sizeof(float);
 
@@ -142,8 +142,8 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     __bf16 *W = reinterpret_cast<__bf16 *>(lds_raw);
     float *bias = reinterpret_cast<float *>(lds_raw + (size_t)kWElems * 2);
-    float *x_mean = bias + kBias, *x_istd = x_mean + 12, *x_lo = x_istd + 12, *x_hi = x_lo + 12;
-    float *y_mean = x_hi + 12, *y_std = y_mean + 12, *cinv = y_std + 12, *maha = cinv + 144;
+    float *x_mean = bias + kBias, *x_istd = x_mean + 12, *z_lo = x_istd + 12, *z_hi = z_lo + 12;
+    float *y_mean = z_hi + 12, *y_std = y_mean + 12, *wht = y_std + 12, *maha = wht + 144;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int p = lane & 15, q = lane >> 4;
     const casim_mlp_stats *S = reinterpret_cast<const casim_mlp_stats *>(stats_raw);
@@ -156,15 +156,17 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
         for (int i = threadIdx.x; i < kBias; i += blockDim.x) bias[i] = bias_g[i];
         if (threadIdx.x < 12) {
             const int j = threadIdx.x;
+            // trust region in standardised units: the range check then tests
+            // the same number the network receives
             const float span = S->x_max[j] - S->x_min[j];
             x_mean[j] = S->x_mean[j];
             x_istd[j] = 1.0f / S->x_std[j];
-            x_lo[j] = S->x_min[j] - range_margin * span;
-            x_hi[j] = S->x_max[j] + range_margin * span;
+            z_lo[j] = (S->x_min[j] - range_margin * span - S->x_mean[j]) / S->x_std[j];
+            z_hi[j] = (S->x_max[j] + range_margin * span - S->x_mean[j]) / S->x_std[j];
             y_mean[j] = S->y_mean[j];
             y_std[j] = S->y_std[j];
         }
-        for (int i = threadIdx.x; i < 144; i += blockDim.x) cinv[i] = S->cov_inv[i];
+        for (int i = threadIdx.x; i < 144; i += blockDim.x) wht[i] = S->whiten[i];
         if (threadIdx.x == 0) maha[0] = maha_max_arg > 0.0f ? maha_max_arg : S->maha_q999;
     }
     __syncthreads();
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
         // them (some 70 values per lane) into registers for the whole loop.
         int oz;
         asm volatile("v_mov_b32 %0, 0" : "=v"(oz));
-        const float *xm = x_mean + oz, *xi = x_istd + oz, *xl = x_lo + oz, *xh = x_hi + oz, *ci = cinv + oz;
+        const float *xm = x_mean + oz, *xi = x_istd + oz, *zl = z_lo + oz, *zh = z_hi + oz, *wi = wht + oz;
         // ---- inputs: point 16 nt + p of the tile, features split over q ----
         u32x4 b[4][4];
         bool fb[4];
@@ -193,20 +195,21 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
                 const float x = valid ? feat[row * 12 + j] : xm[j];
                 z[j] = (x - xm[j]) * xi[j];
             }
-            // range check of features 3q..3q+2 and rows 3q..3q+2 of z^T C^-1 z
-            // (this lane's three features picked by q, not by a register index)
+            // range check of features 3q..3q+2 and rows 3q..3q+2 of W z, whose
+            // squares sum to the squared Mahalanobis distance (this lane's three
+            // features picked by q, not by a register index; W is lower
+            // triangular and its zeros above the diagonal are read as zeros)
             bool out = false;
             float part = 0.0f;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int ja = 3 * q + a;
                 const float za = q == 0 ? z[a] : q == 1 ? z[3 + a] : q == 2 ? z[6 + a] : z[9 + a];
-                const float x = za / xi[ja] + xm[ja];
-                out |= (x < xl[ja]) | (x > xh[ja]);
+                out |= (za < zl[ja]) | (za > zh[ja]);
                 float s_ = 0.0f;
 #pragma unroll
-                for (int c = 0; c < 12; ++c) s_ = fmaf(ci[ja * 12 + c], z[c], s_);
-                part = fmaf(za, s_, part);
+                for (int c = 0; c < 12; ++c) s_ = fmaf(wi[ja * 12 + c], z[c], s_);
+                part = fmaf(s_, s_, part);
             }
             part += __shfl_xor(part, 16);
             part += __shfl_xor(part, 32);
@@ -247,16 +250,17 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
         }
 
         // ---- per point: undo the scaling, gates, signs ----------------------
+        // (the four lanes of a point share p, so they take the same branches;
+        // a non-finite rate anywhere in the point sends it to the plain rates)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const int64_t i0 = t + nt * 16 + p;
-            if (i0 >= cnt) continue;
+            const bool valid = i0 < cnt;
             const int64_t row = r * rcap + i0;
-            if (q == 0) fallback[row] = fb[nt] ? 1 : 0;
-            if (q == 3) continue;
-            const unsigned gw = gates[row];
+            const unsigned gw = valid ? gates[row] : 0u;
             const bool supersat_ice = gw & CASIM_GATE_SUPERSAT_ICE;
             float out4[4];
+            bool bad = false;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int j = 4 * q + e;
@@ -273,11 +277,49 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
                     rv = fmaxf(rv, 0.0f);
                 }
                 out4[e] = ((gw >> j) & 1u) ? rv : 0.0f;
+                bad |= q < 3 && !__builtin_isfinite(out4[e]);
             }
-            *reinterpret_cast<float4 *>(rates + row * 12 + 4 * q) = make_float4(out4[0], out4[1], out4[2], out4[3]);
+            int bi = (int)bad;
+            bi |= __shfl_xor(bi, 16);
+            bi |= __shfl_xor(bi, 32);
+            if (valid) {
+                if (q == 0) fallback[row] = (fb[nt] || bi) ? 1 : 0;
+                if (q < 3)
+                    *reinterpret_cast<float4 *>(rates + row * 12 + 4 * q) =
+                        make_float4(out4[0], out4[1], out4[2], out4[3]);
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
     }
+}
+
+// Per point (k, c): the rates and trust-region flag of its slot, or zeros
+// and flag 2 when it has no slot.  rates_out is [12][nlev][ld], flags
+// [nlev][ld].
+__global__ __launch_bounds__(256) void slot_scatter_kernel(const int32_t *__restrict__ idx_map, int64_t ncol,
+                                                           int64_t nlev, int64_t ld,
+                                                           const float *__restrict__ slot_rates,
+                                                           const uint8_t *__restrict__ slot_fb,
+                                                           float *__restrict__ rates_out,
+                                                           uint8_t *__restrict__ flags) {
+    const int64_t pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pid >= ncol * nlev) return;
+    const int64_t k = pid / ncol, c = pid - k * ncol;
+    const int64_t ix = k * ld + c, plane = nlev * ld;
+    const int32_t slot = idx_map[pid];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) rates_out[j * plane + ix] = slot >= 0 ? slot_rates[(int64_t)slot * 12 + j] : 0.0f;
+    flags[ix] = slot >= 0 ? slot_fb[slot] : (uint8_t)2;
+}
+
+hipError_t launch_slot_scatter(const int32_t *idx_map, int64_t ncol, int64_t nlev, int64_t ld,
+                               const float *slot_rates, const uint8_t *slot_fb, float *rates_out, uint8_t *flags,
+                               hipStream_t stream) {
+    const int64_t n = ncol * nlev, blocks = (n + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(slot_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, idx_map, ncol, nlev, ld,
+                       slot_rates, slot_fb, rates_out, flags);
+    return hipGetLastError();
 }
 
 // ---- host side -------------------------------------------------------------

@@ -58,3 +58,18 @@ def test_nsub_host_logic(L, oracle_lib):
         casim.nsub(dz, 2.0)
     with pytest.raises(casim.CasimError):
         casim.nsub(np.array([10.0]), math.nan)
+
+
+def test_dz_must_match_the_level_count():
+    """The library reads nlev thicknesses through the dz pointer: the binding
+    refuses a dz of another length before any call."""
+    import torch
+    state = torch.zeros((14, 3, 4), dtype=torch.float64)
+    tend = torch.zeros((12, 3, 4), dtype=torch.float64)
+    sfc = torch.zeros((8, 4), dtype=torch.float64)
+    casim.make_state(state, [10.0, 10.0, 10.0], tend, sfc)
+    for dz in ([10.0, 10.0], [10.0] * 4, [[10.0, 10.0, 10.0]]):
+        with pytest.raises(ValueError):
+            casim.make_state(state, dz, tend, sfc)
+    with pytest.raises(ValueError):
+        casim.step_host(np.zeros((14, 3, 4)), [10.0, 10.0], 2.0, np.zeros((12, 3, 4)), np.zeros((8, 4)))

@@ -8,12 +8,16 @@ import numpy as np
 import pytest
 
 from paper_2010_14823_amd import synth
-from util import SFC, TEND, config_state, oracle_steps, run_gpu
+from util import SFC, TEND, config_state, oracle_steps, oracle_ulp_floor, run_gpu
 
 pytestmark = pytest.mark.gpu
 
 STATE = ("T", "qv", "qc", "nc", "qr", "nr", "qi", "ni", "qs", "ns", "qg", "ng")
-BOUND_MAX = 1e-3          # stated bound for the mixed path, every field
+# Stated bounds for the mixed path (normwise, every field), about 10 x the
+# largest errors measured on this workload (state 2.5e-6, tendencies 1.4e-5
+# max; RMS an order of magnitude below)
+BOUND_STATE_MAX, BOUND_TEND_MAX, BOUND_RMS = 3e-5, 2e-4, 2e-5
+BOUND_FP64 = 1e-12        # the binary64 path after 10 coupled steps
 
 
 def _errors(g, o):
@@ -57,9 +61,19 @@ def test_ten_steps_against_oracle(oracle_lib, mode):
     print("%s: tendencies of step %d (max, rms)" % (label, steps))
     for k, v in e_tend.items():
         print("  %-4s %.3e %.3e" % (k, v[0], v[1]))
-    worst = max(max(v[0] for v in e_state.values()), max(v[0] for v in e_tend.values()))
     assert status["nonfinite"] == 0
+    ws = max(v[0] for v in e_state.values())
+    wt = max(v[0] for v in e_tend.values())
+    wr = max(max(v[1] for v in e_state.values()), max(v[1] for v in e_tend.values()))
     if mode == 0:
-        assert worst < 1e-9
+        # 1e-12, or ten times the oracle's own sensitivity to one-ulp
+        # perturbations of the states it steps from (see util.oracle_ulp_floor)
+        floor_t, floor_s = oracle_ulp_floor(oracle_lib, st, dz, cfg.dt, steps)
+        print("fp64 ulp floor: tendencies", {k: float("%.2g" % v) for k, v in floor_t.items()})
+        print("fp64 ulp floor: state", {STATE[j]: float("%.2g" % floor_s[f]) for j, f in enumerate(idx)})
+        for j, f in enumerate(idx):
+            assert e_state[STATE[j]][0] <= max(BOUND_FP64, 10 * floor_s[f]), (STATE[j], e_state[STATE[j]], floor_s[f])
+        for k, v in e_tend.items():
+            assert v[0] <= max(BOUND_FP64, 10 * floor_t[k]), (k, v, floor_t[k])
     else:
-        assert worst < BOUND_MAX
+        assert ws <= BOUND_STATE_MAX and wt <= BOUND_TEND_MAX and wr <= BOUND_RMS, (ws, wt, wr)

@@ -26,7 +26,7 @@ def _sample(ncol, rng):
 @pytest.mark.parametrize("key,mode", [("c3", 0), ("c2", 0), ("c3", 1)])
 def test_full_domain_sampled_columns(oracle_lib, key, mode):
     """mode 0: binary64, bound 1e-12; mode 1: FP32-mixed (rates and fall
-    speeds in float32), bound 1e-3 as for its ten-step test."""
+    speeds in float32), bound 2e-4 as for its ten-step test."""
     import torch
     from paper_2010_14823_amd import casim
     cfg = synth.CONFIGS[key]
@@ -55,7 +55,7 @@ def test_full_domain_sampled_columns(oracle_lib, key, mode):
     errs = field_errors(outs[1][0], outs[1][1], to, so)
     print(key, "mode", mode, "sampled columns", idx.size, {k: float("%.3g" % v) for k, v in errs.items()}, status,
           flush=True)
-    bad = {k: v for k, v in errs.items() if not v <= (TOL if mode == 0 else 1e-3)}
+    bad = {k: v for k, v in errs.items() if not v <= (TOL if mode == 0 else 2e-4)}
     assert not bad, bad
     assert status["nonfinite"] == 0
 

@@ -79,3 +79,26 @@ def test_host_pipeline_argument_errors():
     assert casim.lib().casim_host_alloc(None, 8) == -1
     assert casim.lib().casim_host_alloc(ctypes.byref(p), 64) == 0 and p.value
     assert casim.lib().casim_host_free(p) == 0
+
+
+def test_rejected_call_enqueues_nothing():
+    """A request casim_step would reject (more carry slots than the sweep
+    holds: 512 thin levels at dt = 2 s) fails before any copy is enqueued:
+    the host outputs keep their values."""
+    import torch
+    from paper_2010_14823_amd import casim
+    cfg = synth.Config("levels512", 8, 8, 512, 7, 0.5)
+    f, dz, _ = synth.generate(cfg)
+    st = synth.stack(f)
+    casim.init()
+    hin, hout, hsfc = casim.HostArray(st.shape), casim.HostArray((12, 512, 64)), casim.HostArray((8, 64))
+    hin.array[:] = st
+    hout.array[:] = -7.0
+    hsfc.array[:] = -7.0
+    with pytest.raises(casim.CasimError) as e:
+        casim.step_host(hin.array, dz, 2.0, hout.array, hsfc.array)
+    assert e.value.code == -3
+    torch.cuda.synchronize()
+    assert np.all(hout.array == -7.0) and np.all(hsfc.array == -7.0)
+    for h in (hin, hout, hsfc):
+        h.free()

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2010_14823_amd import synth
-from util import SFC, TEND, config_state, field_errors, oracle_steps, run_gpu
+from util import SFC, TEND, config_state, field_errors, oracle_steps, oracle_ulp_floor, run_gpu
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -112,6 +112,45 @@ def test_warm_configuration(oracle_lib):
         assert np.all(tg[j] == 0.0)
 
 
+def test_warm_configuration_c1_sixteen_column_tiles(oracle_lib):
+    """The compiled-in warm kernel at the tile width the benchmark uses on the
+    large domains: the whole 256 x 256 x 100 domain (65,536 columns select
+    16-column tiles), two steps on the same state so that the second runs in
+    the activity-derived launch order."""
+    import torch
+    from paper_2010_14823_amd import casim
+    cfg, st, dz, _ = config_state("c1")
+    assert st.shape[2] // 16 >= 2048           # the library picks 16-column tiles
+    dev = torch.from_numpy(st).cuda()
+    casim.init(casim.default_constants(warm=1))
+    casim.status()
+    outs = []
+    for _ in range(2):
+        tend = torch.full((12,) + st.shape[1:], -7.0, dtype=torch.float64, device="cuda")
+        sfc = torch.full((8, st.shape[2]), -7.0, dtype=torch.float64, device="cuda")
+        casim.step(dev, dz, cfg.dt, tend, sfc)
+        torch.cuda.synchronize()
+        outs.append((tend.cpu().numpy(), sfc.cpu().numpy()))
+    status = casim.status()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    tg, sg = outs[1]
+    to, so, fails = oracle_lib.step(st, dz, cfg.dt, warm=True, return_fails=True)
+    errs = field_errors(tg, sg, to, so)
+    print("warm c1", {k: float("%.3g" % v) for k, v in errs.items()}, status)
+    assert max(errs.values()) <= TOL, errs
+    assert status["newton_fail"] == 2 * fails and status["nonfinite"] == 0
+    for j in range(6, 12):
+        assert np.all(tg[j] == 0.0)
+
+
+@pytest.mark.parametrize("cols_per_wave", [16, 32])
+def test_warm_configuration_forced_tiles(oracle_lib, cols_per_wave, monkeypatch):
+    monkeypatch.setenv("CASIM_COLS_PER_WAVE", str(cols_per_wave))
+    cfg = synth.Config("warmtiles", 37, 11, 100, 23, 0.5)
+    f, dz, _ = synth.generate(cfg)
+    _assert_parity(oracle_lib, synth.stack(f), dz, 2.0, warm=1, tag="warm C%d" % cols_per_wave)
+
+
 def test_newton_failure_flag(oracle_lib):
     cfg, st, dz, _ = config_state("c0")
     tg, sg, status, _ = run_gpu(st, dz, cfg.dt, newton_iters=1)
@@ -138,12 +177,19 @@ def test_nonfinite_input_counted(oracle_lib):
 
 
 def test_multistep_apply_matches_oracle(oracle_lib):
+    """Four coupled steps.  Per field the bound is 1e-12 or ten times the
+    oracle's own sensitivity to one-ulp perturbations of the states it steps
+    from, whichever is larger: after a step the cloud sits at saturation and
+    the next adjustment's increment is a cancelling difference of q_v and
+    q_sat, which two correctly rounded binary64 evaluations do not share."""
     cfg, st, dz, _ = config_state("c0")
     tg, sg, status, state_after = run_gpu(st, dz, cfg.dt, steps=4)
     to, so = oracle_steps(oracle_lib, st, dz, cfg.dt, steps=4)
     errs = field_errors(tg, sg, to, so)
-    print("4 steps", errs)
-    assert max(errs.values()) <= 1e-10, errs
+    floor, _ = oracle_ulp_floor(oracle_lib, st, dz, cfg.dt, 4)
+    print("4 steps", {k: "%.2g (floor %.2g)" % (v, floor[k]) for k, v in errs.items()})
+    bad = {k: (v, floor[k]) for k, v in errs.items() if not v <= max(TOL, 10 * floor[k])}
+    assert not bad, bad
     # non-negativity of every q and n after the parent-model update
     assert np.all(state_after[3:] >= 0.0)
 
@@ -194,7 +240,7 @@ def test_fp32mix_tiles_agree(oracle_lib, cols_per_wave, monkeypatch):
     to, so = oracle_lib.step(st, dz, cfg.dt)
     errs = field_errors(tg, sg, to, so)
     print("fp32mix C=%d" % cols_per_wave, {k: float("%.3g" % v) for k, v in errs.items()})
-    assert max(errs.values()) < 1e-3, errs
+    assert max(errs.values()) < 6e-5, errs        # measured 5.7e-6 (dng)
 
 
 @pytest.mark.parametrize("mode", [0, 1])

@@ -74,3 +74,36 @@ def oracle_steps(oracle, state_np, dz, dt, steps=1, **kw):
                 v = st[f + 2] + dt * tend[f]
                 st[f + 2] = np.where(v > 0.0, v, 0.0)
     return tend, sfc
+
+
+def oracle_ulp_floor(oracle, state_np, dz, dt, steps, seed=0, **kw):
+    """How far the oracle's own multi-step answer moves when every state it
+    steps from is perturbed by one unit in the last place (relative 2^-52,
+    random sign, T and the 12 prognostic fields): per tendency/surface field
+    the normwise change of the last step's outputs, and per state field the
+    change of the state after steps - 1 updates.  Two correct binary64
+    implementations that round differently differ by about this much: near
+    saturation the adjustment's increment is a small difference of q_v and
+    q_sat, so after a few coupled steps a one-ulp change of q_v moves the
+    tendencies by far more than one ulp of their own size."""
+    rng = np.random.default_rng(seed)
+
+    def run(perturb):
+        st = state_np.copy()
+        for s in range(steps):
+            if perturb:
+                for f in [0] + list(range(3, 14)):
+                    st[f] = st[f] * (1.0 + rng.choice([-1.0, 1.0], size=st[f].shape) * 2.0 ** -52)
+            tend, sfc = oracle.step(st, dz, dt, **kw)
+            if s + 1 < steps:
+                st[0] = st[0] + dt * tend[0]
+                for f in range(1, 12):
+                    v = st[f + 2] + dt * tend[f]
+                    st[f + 2] = np.where(v > 0.0, v, 0.0)
+        return tend, sfc, st
+    t0, s0, x0 = run(False)
+    t1, s1, x1 = run(True)
+    errs = field_errors(t1, s1, t0, s0)
+    idx = [0] + list(range(3, 14))
+    state_errs = {f: normwise(x1[f], x0[f]) for f in idx}
+    return errs, state_errs
