@@ -179,6 +179,23 @@ int casim_init(const casim_constants *c, const casim_thresholds *t);
  * anything is enqueued.  ncol == 0 is a no-op. */
 int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream);
 
+/* casim_step for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same kernels and results as casim_step (bitwise), for modes CASIM_MODE_FP64
+ * and CASIM_MODE_FP32MIX (others: EINVAL); the call itself allocates nothing.
+ * Everything beyond the caller's inputs and outputs (the device copy of dz,
+ * the step counters that casim_status reads, the per-tile activity record and
+ * launch order) lives in one statically sized device array per GPU, set up by
+ * casim_init on the GPU that is current then; a call on another GPU returns
+ * ENOINIT.  Limit: at most 262,144 column tiles (4,194,304 columns at the
+ * 16-column tiles of large domains; fewer on narrow tiles), else ECAPACITY.
+ * All calls on one GPU share that array and it keeps the last call's
+ * contents: calls whose execution overlaps on one GPU (other streams, other
+ * host threads) race on it and must be ordered by the caller.  dz is a host
+ * pointer, copied to the array with an asynchronous copy on `stream`.
+ * Errors: as casim_step. */
+int casim_step_noalloc(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream);
+
 /* Parent-model helper for multi-step runs: X += dt * tend for the 12
  * prognostic fields of `s` (in[] is written through a cast: it must be
  * writable memory), q and n clipped at 0.  Errors as casim_step. */

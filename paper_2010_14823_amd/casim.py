@@ -105,6 +105,7 @@ def lib():
             "casim_default_thresholds": [ctypes.POINTER(Thresholds)],
             "casim_init": [ctypes.POINTER(Constants), ctypes.POINTER(Thresholds)],
             "casim_step": [ctypes.POINTER(State), i64, i32, dbl, vp],
+            "casim_step_noalloc": [ctypes.POINTER(State), i64, i32, dbl, vp],
             "casim_step_host": [ctypes.POINTER(HostState), i64, i32, dbl, i32, vp],
             "casim_host_alloc": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t],
             "casim_host_free": [vp],
@@ -243,6 +244,16 @@ def step(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
     st = make_state(state, dz, tend, sfc, ld)
     _check(lib().casim_step(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
            "casim_step")
+
+
+def step_noalloc(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
+    """Enqueue casim_step_noalloc (no device allocation in the call)."""
+    nlev, ld = state.shape[1], state.shape[2]
+    ncol = ld if ncol is None else int(ncol)
+    _check_tensors(state, tend, sfc, ncol)
+    st = make_state(state, dz, tend, sfc, ld)
+    _check(lib().casim_step_noalloc(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
+           "casim_step_noalloc")
 
 
 def apply_tendencies(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):

@@ -43,10 +43,7 @@ struct Context {
     // derived from it; the activity is reused only for the same domain
     int32_t *d_busy = nullptr, *d_order = nullptr;
     int64_t tile_cap = 0;
-    bool hist = false;
-    const void *hist_in0 = nullptr;
-    int64_t hist_ncol = 0, hist_ld = 0;
-    int32_t hist_nlev = 0, hist_mode = -1, hist_warm = -1;
+    bool hist = false;                      // false: the tile history is void
     int reserve_tiles = 0;
     // host-state pipeline: streams, events and two device buffer sets, each
     // [14 + 12][pipe_lev][pipe_ld] fields and [8][pipe_ld] surface values
@@ -296,17 +293,17 @@ int ensure_tiles(int64_t ntiles) {
     return CASIM_OK;
 }
 
-// Tile order for this step (from the last step's activity when it ran on the
-// same domain) and activity recording for the next.  CASIM_TILE_ORDER=0 in
-// the environment keeps the identity order; CASIM_XCDS sets the number of
-// XCDs the block renumbering assumes (default 8, the XCDs of an MI355X; 1
-// turns it off) and CASIM_XCD_GROUP its group size in blocks.
-int plan_tiles(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, hipStream_t st) {
-    SweepGeometry geo;
-    HIP_TRY(sweep_geometry(ncol, a.nslots, &geo));
-    const int64_t ntiles = geo.tiles;
-    int rc = ensure_tiles(ntiles);
-    if (rc) return rc;
+// Launch shape of the sweep's blocks: the number of XCDs the block
+// renumbering assumes, its group size in blocks, and the clear tiles kept for
+// each XCD's last dispatch round.  CASIM_XCDS sets the XCD count (default 8,
+// the XCDs of an MI355X; 1 turns the renumbering off), CASIM_XCD_GROUP forces
+// the group size.
+struct TilePlan {
+    int nxcd = kXcds, group = kXcdGroupMin;
+    int64_t reserve = 0;
+};
+
+int tile_plan(const SweepGeometry &geo, TilePlan &tp) {
     static const int nxcd = [] {
         const char *e = getenv("CASIM_XCDS");
         const int v = e ? atoi(e) : kXcds;
@@ -327,34 +324,105 @@ int plan_tiles(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, h
         group = kXcdGroupMin;
         while (group < kXcdGroupMax && geo.blocks / ((int64_t)nxcd * 16) >= 2 * group) group *= 2;
     }
-    a.nxcd = nxcd;
-    a.xcd_group = group;
     if (!g.reserve_tiles) {
         int cus = 0;
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g.device));
         g.reserve_tiles = 12 * (cus > 0 ? cus : 1);       // one dispatch round: 3 wavefronts x 4 SIMDs per CU
     }
-    // one dispatch round of one XCD's compute units
-    const int64_t reserve = (g.reserve_tiles + nxcd - 1) / nxcd;
-    static const int enabled = [] { const char *e = getenv("CASIM_TILE_ORDER"); return e ? atoi(e) : 1; }();
-    const bool same = g.hist && g.hist_in0 == (const void *)s->in[0] && g.hist_ncol == ncol &&
-                      g.hist_ld == s->ld && g.hist_nlev == nlev && g.hist_mode == g.c.mode &&
-                      g.hist_warm == g.c.warm;
-    a.ntiles = ntiles;
-    a.tile_busy = g.d_busy;
-    a.order = nullptr;
-    if (same && enabled) {
-        HIP_TRY(launch_tile_order(g.d_busy, geo, nxcd, group, reserve, g.d_order, st));
-        a.order = g.d_order;
-    }
-    g.hist = true;
-    g.hist_in0 = s->in[0];
-    g.hist_ncol = ncol;
-    g.hist_ld = s->ld;
-    g.hist_nlev = nlev;
-    g.hist_mode = g.c.mode;
-    g.hist_warm = g.c.warm;
+    tp.nxcd = nxcd;
+    tp.group = group;
+    tp.reserve = (g.reserve_tiles + nxcd - 1) / nxcd;    // one dispatch round of one XCD's compute units
     return CASIM_OK;
+}
+
+bool tile_order_enabled() {
+    static const int enabled = [] { const char *e = getenv("CASIM_TILE_ORDER"); return e ? atoi(e) : 1; }();
+    return enabled != 0;
+}
+
+// What a step's per-tile activity record belongs to: the next step reuses it
+// for its launch order only on the same domain, mode and configuration.
+struct TileHistory {
+    bool valid = false;
+    const void *in0 = nullptr;
+    int64_t ncol = 0, ld = 0;
+    int32_t nlev = 0, mode = -1, warm = -1;
+    bool same(const casim_state *s, int64_t nc, int32_t nl) const {
+        return valid && in0 == (const void *)s->in[0] && ncol == nc && ld == s->ld && nlev == nl &&
+               mode == g.c.mode && warm == g.c.warm;
+    }
+    void record(const casim_state *s, int64_t nc, int32_t nl) {
+        valid = true; in0 = s->in[0]; ncol = nc; ld = s->ld; nlev = nl; mode = g.c.mode; warm = g.c.warm;
+    }
+};
+
+// Tile order for this step (from the last step's activity when it ran on the
+// same domain) and activity recording for the next, with the per-tile
+// buffers busy / order (ntiles entries each) and their history hist.
+int plan_tiles_with(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, int32_t *busy, int32_t *order,
+                    TileHistory &hist, hipStream_t st) {
+    SweepGeometry geo;
+    HIP_TRY(sweep_geometry(ncol, a.nslots, &geo));
+    TilePlan tp;
+    int rc = tile_plan(geo, tp);
+    if (rc) return rc;
+    a.nxcd = tp.nxcd;
+    a.xcd_group = tp.group;
+    a.ntiles = geo.tiles;
+    a.tile_busy = busy;
+    a.order = nullptr;
+    if (hist.same(s, ncol, nlev) && tile_order_enabled()) {
+        HIP_TRY(launch_tile_order(busy, geo, tp.nxcd, tp.group, tp.reserve, order, st));
+        a.order = order;
+    }
+    hist.record(s, ncol, nlev);
+    return CASIM_OK;
+}
+
+TileHistory g_hist;        // history of the library-owned tile buffers
+
+// ---- scratch of the allocation-free step ---------------------------------
+// One statically allocated device array per GPU holds everything
+// casim_step_noalloc needs beyond the caller's inputs and outputs: the
+// device copy of dz, the step's four counters, and the per-tile activity
+// record and launch order.  In host code `scratch` names a host-side stand-in
+// of the symbol, never device memory: its device address on each GPU comes
+// from hipGetSymbolAddress at initialisation and is kept in g_scratch[device].
+constexpr int kNoAllocMaxTiles = 1 << 18;      // 4,194,304 columns at 16-column tiles
+constexpr size_t kScrDz = 0;                                       // CASIM_MAX_NLEV doubles
+constexpr size_t kScrStatus = kScrDz + sizeof(double) * CASIM_MAX_NLEV;     // 4 counters
+constexpr size_t kScrBusy = kScrStatus + 256;                      // int32 [kNoAllocMaxTiles]
+constexpr size_t kScrOrder = kScrBusy + sizeof(int32_t) * kNoAllocMaxTiles; // int32 [kNoAllocMaxTiles]
+constexpr size_t kScratchBytes = kScrOrder + sizeof(int32_t) * kNoAllocMaxTiles;
+constexpr int kMaxDevices = 64;
+static_assert(kScrStatus % 256 == 0 && kScrBusy % 256 == 0 && kScrOrder % 256 == 0, "scratch layout");
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+unsigned char *g_scratch[kMaxDevices] = {};   // device address of `scratch` on each GPU
+TileHistory g_scratch_hist[kMaxDevices];
+
+// Called with device `dev` current (from casim_init).
+int scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return CASIM_ECAPACITY;
+    if (g_scratch[dev]) return CASIM_OK;
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return CASIM_EHIP;
+    g_scratch[dev] = static_cast<unsigned char *>(p);
+    g_scratch_hist[dev].valid = false;
+    return CASIM_OK;
+}
+
+int plan_tiles(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, hipStream_t st) {
+    SweepGeometry geo;
+    HIP_TRY(sweep_geometry(ncol, a.nslots, &geo));
+    int rc = ensure_tiles(geo.tiles);
+    if (rc) return rc;
+    if (!g.hist) g_hist.valid = false;
+    rc = plan_tiles_with(s, ncol, nlev, a, g.d_busy, g.d_order, g_hist, st);
+    g.hist = true;
+    return rc;
 }
 
 // The surrogate step's rate path: features and gates of every point that
@@ -441,6 +509,8 @@ int casim_init(const casim_constants *c, const casim_thresholds *t) {
         g.h_dz.clear();
         g.device = dev;
     }
+    if ((rc = scratch_setup(dev))) return rc;
+    for (auto &h : g_scratch_hist) h.valid = false;     // new constants or mode: index order first
     g.c = *c;
     g.t = *t;
     g.P = derive(*c, *t, gamma_table(*c));
@@ -511,6 +581,47 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
         a.cmp_ld = g.cmp_cap;
     }
     if ((rc = plan_tiles(s, ncol, nlev, a, st))) return rc;
+    HIP_TRY(launch_sweep(g.P, g.fast, a, st));
+    return CASIM_OK;
+}
+
+int casim_step_noalloc(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream) {
+    int rc = check_state(s, ncol, nlev, dt);
+    if (rc) return rc;
+    if (g.c.mode != CASIM_MODE_FP64 && g.c.mode != CASIM_MODE_FP32MIX) return CASIM_EINVAL;
+    if (ncol == 0) return CASIM_OK;
+    if (!s->dz) return CASIM_EINVAL;
+    for (int f = 0; f < CASIM_NSFC; ++f)
+        if (!s->sfc[f]) return CASIM_EINVAL;
+    for (int k = 0; k < nlev; ++k)
+        if (!pos_finite(s->dz[k])) return CASIM_EINVAL;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices || !g_scratch[dev]) return CASIM_ENOINIT;   // casim_init ran on another GPU
+    unsigned char *scr = g_scratch[dev];
+    SweepArgs a{};
+    fill_args(s, ncol, nlev, dt, a);
+    nsub_of(g.c, s->dz, nlev, dt, a.nsub);
+    for (int j = 0; j < 4; ++j) a.dts[j] = dt / a.nsub[j];
+    int slot = 0;
+    for (int j = 0; j < 4; ++j) {
+        a.slot0[j] = slot;
+        slot += 2 * a.nsub[j];
+    }
+    a.nslots = slot;
+    if (slot > kMaxCarrySlots) return CASIM_ECAPACITY;
+    SweepGeometry geo;
+    HIP_TRY(sweep_geometry(ncol, a.nslots, &geo));
+    if (geo.tiles > kNoAllocMaxTiles) return CASIM_ECAPACITY;
+    hipStream_t st = (hipStream_t)stream;
+    // the vertical grid goes into the scratch with the step (4 KB at most)
+    double *dz_d = reinterpret_cast<double *>(scr + kScrDz);
+    HIP_TRY(hipMemcpyAsync(dz_d, s->dz, sizeof(double) * nlev, hipMemcpyHostToDevice, st));
+    a.dz = dz_d;
+    a.status = reinterpret_cast<unsigned long long *>(scr + kScrStatus);
+    rc = plan_tiles_with(s, ncol, nlev, a, reinterpret_cast<int32_t *>(scr + kScrBusy),
+                         reinterpret_cast<int32_t *>(scr + kScrOrder), g_scratch_hist[dev], st);
+    if (rc) return rc;
     HIP_TRY(launch_sweep(g.P, g.fast, a, st));
     return CASIM_OK;
 }
@@ -684,10 +795,18 @@ int casim_apply_tendencies(const casim_state *s, int64_t ncol, int32_t nlev, dou
 int casim_status(void *stream, casim_step_status *out) {
     if (!g.init) return CASIM_ENOINIT;
     if (!out) return CASIM_EINVAL;
-    unsigned long long h[4];
+    unsigned long long h[4], hs[4] = {0, 0, 0, 0};
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     HIP_TRY(hipMemcpy(h, g.d_status, sizeof h, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemset(g.d_status, 0, sizeof h));
+    // and the counters of the allocation-free step on the current device
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev >= 0 && dev < kMaxDevices && g_scratch[dev]) {
+        HIP_TRY(hipMemcpy(hs, g_scratch[dev] + kScrStatus, sizeof hs, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemset(g_scratch[dev] + kScrStatus, 0, sizeof hs));
+        for (int j = 0; j < 4; ++j) h[j] += hs[j];
+    }
     out->newton_fail = (int64_t)h[0];
     out->nonfinite = (int64_t)h[1];
     out->fallback = (int64_t)h[2];
