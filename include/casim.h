@@ -25,6 +25,10 @@
  *    [k][ld] with the column index fastest (element (k, c) at k*ld + c),
  *    k = 0 the lowest level.  The caller owns all field memory; the library
  *    never frees it and reads/writes it only inside enqueued work.
+ *  - Citations: each declaration names the passage of the paper that defines
+ *    what it does; "[proposal]" marks an entry point the paper does not
+ *    describe (diagnostics, error text, the learned surrogate), whose form
+ *    is this library's own choice.
  */
 #ifndef CASIM_H
 #define CASIM_H
@@ -158,7 +162,8 @@ typedef struct casim_step_status {
     int64_t inferred;       /* surrogate points that used the network     */
 } casim_step_status;
 
-/* Fill *c / *t with the default published values.  Never fails on non-NULL. */
+/* [proposal] Fill *c / *t with the default published values named beside
+ * each field (the paper prints no constants).  Never fails on non-NULL. */
 int casim_default_constants(casim_constants *c);
 int casim_default_thresholds(casim_thresholds *t);
 
@@ -196,28 +201,36 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
  * Errors: as casim_step. */
 int casim_step_noalloc(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream);
 
-/* Parent-model helper for multi-step runs: X += dt * tend for the 12
- * prognostic fields of `s` (in[] is written through a cast: it must be
- * writable memory), q and n clipped at 0.  Errors as casim_step. */
+/* Parent-model helper for multi-step runs (Sec. II-A: the parent model sums
+ * the source terms its components return and integrates them into the
+ * prognostic fields): X += dt * tend for the 12 prognostic fields of `s`
+ * (in[] is written through a cast: it must be writable memory), q and n
+ * clipped at 0.  Errors as casim_step. */
 int casim_apply_tendencies(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream);
 
-/* Synchronise `stream`, copy the device counters into *out and reset them.
- * Errors: ENOINIT, EINVAL (NULL out), EHIP. */
+/* [proposal] Synchronise `stream`, copy the device counters into *out and
+ * reset them (those of casim_step and of casim_step_noalloc on the current
+ * GPU).  Errors: ENOINIT, EINVAL (NULL out), EHIP. */
 int casim_status(void *stream, casim_step_status *out);
 
-/* Free library-owned device memory (never caller memory).  Safe to call
- * twice. */
+/* Shutdown (Sec. III-B: the finalisation routine closes the device data
+ * region and releases the device memory it holds): frees library-owned
+ * device memory, never caller memory.  Safe to call twice. */
 int casim_finalize(void);
 
-/* Static text for a code; for CASIM_EHIP, the last HIP error seen. */
+/* [proposal] Static text for a code; for CASIM_EHIP, the last HIP error seen. */
 const char *casim_strerror(int code);
 
-/* Number of sedimentation substeps per category r, i, s, g that casim_step
- * uses for this grid and dt: max(1, ceil(v_max dt / min dz)).  Host only. */
+/* [proposal] Number of sedimentation substeps per category r, i, s, g that
+ * casim_step uses for this grid and dt (sedimentation advances in
+ * sub-timesteps, Sec. II; the static count max(1, ceil(v_max dt / min dz))
+ * is this library's reading).  Host only. */
 int casim_nsub(const double *dz_host, int32_t nlev, double dt, int32_t nsub_out[4]);
 
 /* ======================================================================
- * Learned surrogate of the process-rate block.
+ * [proposal] Learned surrogate of the process-rate block (every entry point
+ * of this section).  The paper has no learned component; this one replaces
+ * the rate block of the scheme whose processes Sec. II lists.
  *
  * A multilayer perceptron maps a grid point's state after saturation
  * adjustment to its 12 process rates (AUTO ACCR REVP DEPI DEPS IAUT SACI SACW
@@ -319,14 +332,16 @@ int casim_surrogate_load(void);
 
 /* Inference on n samples: rates (n x 12, kg/kg/s) from the bfloat16 network
  * with closed gates zeroed, rates kept non-negative (deposition rates keep
- * the sign of the ice supersaturation), and fallback[i] = 1 where a feature
- * lies outside the training range widened by sur_range_margin on each side
- * or the squared Mahalanobis distance exceeds the threshold (sur_maha_max,
- * or the training 99.9th percentile when that is 0). */
+ * the sign of the ice supersaturation), and fallback[i] = 1 where a
+ * standardised feature lies outside the standardised training range widened
+ * by sur_range_margin of the range on each side, where the squared
+ * Mahalanobis distance |W z|^2 exceeds the threshold (sur_maha_max, or the
+ * training 99.9th percentile when that is 0), or where a rate comes out
+ * non-finite. */
 int casim_surrogate_infer(const float *feat, const uint16_t *gates, int64_t n, float *rates,
                           uint8_t *fallback, void *stream);
 
-/* The rates a CASIM_MODE_SURROGATE step would take from the network, per
+/* [proposal] The rates a CASIM_MODE_SURROGATE step would take from the network, per
  * point, through the step's own path (point pass -> slot -> network), for
  * inspection and testing: rates is a device array [12][nlev][ld] of float32
  * (kg/kg/s, gates and sign rules applied), flags a device array [nlev][ld]
@@ -373,12 +388,13 @@ typedef struct casim_host_state {
 int casim_step_host(const casim_host_state *hs, int64_t ncol, int32_t nlev, double dt, int32_t nblocks,
                     void *stream);
 
-/* Page-locked host memory for casim_step_host (hipHostMalloc); *p is NULL on
- * failure.  Errors: EINVAL (NULL p), EHIP. */
+/* [proposal] Page-locked host memory for casim_step_host (hipHostMalloc),
+ * which the asynchronous copies of Sec. III-B need; *p is NULL on failure.
+ * Errors: EINVAL (NULL p), EHIP. */
 int casim_host_alloc(void **p, size_t bytes);
 int casim_host_free(void *p);
 
-/* Diagnostics: evaluate the binary64 exponential and logarithm that the
+/* [proposal] Diagnostics: evaluate the binary64 exponential and logarithm that the
  * step kernels use internally, elementwise on n device values x (x > 0 for a
  * meaningful log), into device arrays exp_out and log_out (either may be
  * NULL).  Lets callers check their accuracy against a host library.
