@@ -238,7 +238,8 @@ int casim_nsub(const double *dz_host, int32_t nlev, double dt, int32_t nsub_out[
  * ln rho, ln(q + 1e-12) for qv, qc, then ln(n + 1) for nc, and likewise
  * (q, n) for rain and ice, then ln(q + 1e-12) for snow and graupel (feature
  * order T, p, rho, qv, qc, nc, qr, nr, qi, ni, qs, qg).  Targets:
- * asinh(rate / 1e-12 kg kg-1 s-1).  Gate word (uint16): bit j set when rate
+ * asinh(rate / 1e-12 kg kg-1 s-1), of |rate| for DEPI and DEPS (their sign is
+ * the gate word's bit 12).  Gate word (uint16): bit j set when rate
  * j's condition holds (its categories present and its temperature side);
  * bit 12 set when the point is supersaturated over ice.  Closed gates are
  * exact zeros in the plain method and are masked out of training.
@@ -387,6 +388,16 @@ typedef struct casim_host_state {
 
 int casim_step_host(const casim_host_state *hs, int64_t ncol, int32_t nlev, double dt, int32_t nblocks,
                     void *stream);
+
+/* Where the time of the last casim_step_host went (the split the paper
+ * reports per step, Sec. III-C table of copy-on, kernel and copy-off times):
+ * the summed durations of its inbound copies, its steps and its outbound
+ * copies over all column blocks, in ms, from events on the three internal
+ * streams (the three overlap in time, so their sum exceeds the call's wall
+ * time).  Waits for those events.  *nblocks (may be NULL) receives the
+ * number of blocks.  Zeros before any casim_step_host.  Errors: EINVAL (NULL
+ * outputs), EHIP. */
+int casim_host_times(double *h2d_ms, double *step_ms, double *d2h_ms, int32_t *nblocks);
 
 /* [proposal] Page-locked host memory for casim_step_host (hipHostMalloc),
  * which the asynchronous copies of Sec. III-B need; *p is NULL on failure.

@@ -18,7 +18,9 @@ network's output.  Around the network (oracle/mlp.py) this module defines:
 * the training statistics: feature means and population standard deviations
   (floored at 1e-6), feature minima and maxima, means and population standard
   deviations (floored at 1e-3; 0 and 1 when a rate never occurs) of the scaled
-  targets asinh(rate / 1e-12) over open gates, the covariance C of the
+  targets asinh(rate / 1e-12) over open gates (for the two deposition rates
+  the magnitude's: their sign is the gate word's, so the network learns only
+  how large they are), the covariance C of the
   features standardised with those (float32) statistics (divisor n - 1), the
   squared Mahalanobis distance z^T (C + 1e-9 I)^-1 z, and its 99.9th
   percentile, taken as the ceil(0.999 n)-th smallest value.  The statistics
@@ -90,7 +92,12 @@ def gate_word(state12, p, qsat_liquid, qsat_ice, warm=False):
 
 
 def scaled_targets(rates):
-    return np.arcsinh(np.asarray(rates, dtype=np.float64) / RATE_SCALE)
+    """Training targets asinh(rate / 1e-12); for deposition onto ice and snow
+    (rates 3, 4) of the magnitude, whose sign the gate word carries."""
+    r = np.array(rates, dtype=np.float64)
+    r[..., DEPI] = np.abs(r[..., DEPI])
+    r[..., DEPS] = np.abs(r[..., DEPS])
+    return np.arcsinh(r / RATE_SCALE)
 
 
 def fit_stats(feat, rates, gates):

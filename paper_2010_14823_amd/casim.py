@@ -130,6 +130,8 @@ def lib():
             "casim_surrogate_load": [],
             "casim_surrogate_infer": [vp, vp, i64, vp, vp, vp],
             "casim_surrogate_rates": [ctypes.POINTER(State), i64, i32, dbl, vp, vp, vp],
+            "casim_host_times": [ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                 ctypes.POINTER(ctypes.c_int32)],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -454,3 +456,12 @@ def step_host(state, dz, dt: float, tend, sfc, ncol: int | None = None, nblocks:
     hs.ld = ld
     _check(lib().casim_step_host(ctypes.byref(hs), ncol, nlev, float(dt), int(nblocks), _stream_handle(stream)),
            "casim_step_host")
+
+
+def host_times():
+    """(h2d_ms, step_ms, d2h_ms, nblocks) of the last casim_step_host."""
+    h, k, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    nb = ctypes.c_int32()
+    _check(lib().casim_host_times(ctypes.byref(h), ctypes.byref(k), ctypes.byref(d), ctypes.byref(nb)),
+           "casim_host_times")
+    return h.value, k.value, d.value, nb.value

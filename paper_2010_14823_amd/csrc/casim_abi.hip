@@ -52,6 +52,10 @@ struct Context {
     hipEvent_t ev_start = nullptr, ev_in[2] = {}, ev_comp[2] = {}, ev_free[2] = {};
     double *d_pipe[2] = {};
     int64_t pipe_ld = 0, pipe_lev = 0;
+    // timing events of the last casim_step_host: per block, start and end of
+    // its inbound copies, its step and its outbound copies
+    std::vector<hipEvent_t> tev;
+    int64_t tev_blocks = 0;
 };
 
 Context g;
@@ -253,6 +257,9 @@ int pipe_create() {
 void pipe_destroy() {
     if (!g.pipe_ready) return;
     hipDeviceSynchronize();
+    for (hipEvent_t e : g.tev) hipEventDestroy(e);
+    g.tev.clear();
+    g.tev_blocks = 0;
     hipStreamDestroy(g.s_in); hipStreamDestroy(g.s_comp); hipStreamDestroy(g.s_out);
     hipEventDestroy(g.ev_start);
     for (int j = 0; j < 2; ++j) {
@@ -262,6 +269,16 @@ void pipe_destroy() {
     }
     g.pipe_ld = g.pipe_lev = 0;
     g.pipe_ready = false;
+}
+
+// Six timing events per column block of casim_step_host.
+int ensure_timing_events(int64_t nb) {
+    while ((int64_t)g.tev.size() < 6 * nb) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        g.tev.push_back(e);
+    }
+    return CASIM_OK;
 }
 
 int ensure_pipe(int64_t ld, int64_t nlev) {
@@ -661,6 +678,8 @@ int casim_step_host(const casim_host_state *hs, int64_t ncol, int32_t nlev, doub
     int rc = pipe_create();
     if (rc) return rc;
     if ((rc = ensure_pipe(bw, nlev))) return rc;
+    if ((rc = ensure_timing_events(nb))) return rc;
+    g.tev_blocks = 0;
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(g.ev_start, st));
     HIP_TRY(hipStreamWaitEvent(g.s_in, g.ev_start, 0));
@@ -677,26 +696,54 @@ int casim_step_host(const casim_host_state *hs, int64_t ncol, int32_t nlev, doub
         ds.dz = hs->dz;
         ds.ld = g.pipe_ld;
         // inbound: buffer set j is free once block b-2's outbound copies are done
+        hipEvent_t *te = &g.tev[6 * b];
         if (b >= 2) HIP_TRY(hipStreamWaitEvent(g.s_in, g.ev_free[j], 0));
+        HIP_TRY(hipEventRecord(te[0], g.s_in));
         for (int f = 0; f < CASIM_NIN; ++f)
             HIP_TRY(hipMemcpy2DAsync(const_cast<double *>(ds.in[f]), dp, hs->in[f] + c0, hp, sizeof(double) * nc,
                                      nlev, hipMemcpyHostToDevice, g.s_in));
+        HIP_TRY(hipEventRecord(te[1], g.s_in));
         HIP_TRY(hipEventRecord(g.ev_in[j], g.s_in));
         // step
         HIP_TRY(hipStreamWaitEvent(g.s_comp, g.ev_in[j], 0));
+        HIP_TRY(hipEventRecord(te[2], g.s_comp));
         if ((rc = casim_step(&ds, nc, nlev, dt, g.s_comp))) return rc;
+        HIP_TRY(hipEventRecord(te[3], g.s_comp));
         HIP_TRY(hipEventRecord(g.ev_comp[j], g.s_comp));
         // outbound
         HIP_TRY(hipStreamWaitEvent(g.s_out, g.ev_comp[j], 0));
+        HIP_TRY(hipEventRecord(te[4], g.s_out));
         for (int f = 0; f < CASIM_NTEND; ++f)
             HIP_TRY(hipMemcpy2DAsync(hs->tend[f] + c0, hp, ds.tend[f], dp, sizeof(double) * nc, nlev,
                                      hipMemcpyDeviceToHost, g.s_out));
         for (int f = 0; f < CASIM_NSFC; ++f)
             HIP_TRY(hipMemcpyAsync(hs->sfc[f] + c0, ds.sfc[f], sizeof(double) * nc, hipMemcpyDeviceToHost, g.s_out));
+        HIP_TRY(hipEventRecord(te[5], g.s_out));
         HIP_TRY(hipEventRecord(g.ev_free[j], g.s_out));
+        g.tev_blocks = b + 1;
     }
     // the outbound stream is in order, so its last event covers every block
     HIP_TRY(hipStreamWaitEvent(st, g.ev_free[(nb - 1) & 1], 0));
+    return CASIM_OK;
+}
+
+int casim_host_times(double *h2d_ms, double *step_ms, double *d2h_ms, int32_t *nblocks) {
+    if (!h2d_ms || !step_ms || !d2h_ms) return CASIM_EINVAL;
+    *h2d_ms = *step_ms = *d2h_ms = 0.0;
+    if (nblocks) *nblocks = (int32_t)g.tev_blocks;
+    if (!g.pipe_ready || g.tev_blocks == 0) return CASIM_OK;
+    double sum[3] = {0.0, 0.0, 0.0};
+    for (int64_t b = 0; b < g.tev_blocks; ++b) {
+        for (int k = 0; k < 3; ++k) {
+            HIP_TRY(hipEventSynchronize(g.tev[6 * b + 2 * k + 1]));
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, g.tev[6 * b + 2 * k], g.tev[6 * b + 2 * k + 1]));
+            sum[k] += ms;
+        }
+    }
+    *h2d_ms = sum[0];
+    *step_ms = sum[1];
+    *d2h_ms = sum[2];
     return CASIM_OK;
 }
 

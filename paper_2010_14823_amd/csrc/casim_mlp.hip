@@ -227,7 +227,14 @@ __global__ __launch_bounds__(256) void stats_features(const float *feat, int64_t
     }
 }
 
-// Per-target count, sum and sum of squares of asinh(rate / scale) over the
+// Scaled training target of rate j: asinh(rate / scale), of the magnitude for
+// the two deposition rates (DEPI, DEPS), whose sign the gate word carries
+// (bit 12: supersaturated over ice) and inference restores.
+__device__ __forceinline__ double scaled_target(double rate, int j) {
+    return asinh((j == 3 || j == 4 ? fabs(rate) : rate) * kRateScaleInv);
+}
+
+// Per-target count, sum and sum of squares of the scaled target over the
 // samples whose gate is open: one block per target.  out[j*4 + 0..2].
 __global__ __launch_bounds__(256) void stats_targets(const float *rates, const uint16_t *gates, int64_t n,
                                                      double *out) {
@@ -236,7 +243,7 @@ __global__ __launch_bounds__(256) void stats_targets(const float *rates, const u
     double cnt = 0, s = 0, ss = 0;
     for (int64_t i = threadIdx.x; i < n; i += 256) {
         if (!((gates[i] >> j) & 1u)) continue;
-        const double v = asinh((double)rates[i * 12 + j] * kRateScaleInv);
+        const double v = scaled_target((double)rates[i * 12 + j], j);
         cnt += 1.0; s += v; ss += v * v;
     }
     r0[threadIdx.x] = cnt; r1[threadIdx.x] = s; r2[threadIdx.x] = ss;
@@ -312,7 +319,7 @@ __global__ void prepare_kernel(const float *feat, const float *rates, const uint
     x[i] = (feat[i] - S->x_mean[j]) / S->x_std[j];
     const bool open = (gates[p] >> j) & 1u;
     m[i] = open ? 1.0f : 0.0f;
-    y[i] = open ? ((float)asinh((double)rates[i] * kRateScaleInv) - S->y_mean[j]) / S->y_std[j] : 0.0f;
+    y[i] = open ? ((float)scaled_target((double)rates[i], j) - S->y_mean[j]) / S->y_std[j] : 0.0f;
 }
 
 // ---- host side -------------------------------------------------------------------

@@ -86,36 +86,86 @@ __device__ __forceinline__ u32x4 silu_to_operand(const f32x4 &c0, const f32x4 &c
 
 __device__ __forceinline__ bf16x8 as_bf16x8(const u32x4 &v) { return __builtin_bit_cast(bf16x8, v); }
 
-// acc[mt][nt] = bias + W(rows of tiles mt) * B for a 128-wide layer with KS K-steps.
-template <int KS>
-__device__ __forceinline__ void hidden_layer(const __bf16 *W, int w_row, const float *bias, const u32x4 (&b)[4][4],
-                                             f32x4 (&acc)[8][4], int p, int q) {
+// One stage of a hidden layer: the products of output tiles 2j, 2j+1
+// (acc0/acc1 = bias + W(rows of those tiles) * B, four point tiles, KS
+// K-steps) written in program order together with the activation of the
+// previous pair (prev0/prev1 -> bout[j - 1]): after every product pair of a
+// K-step comes a share of the previous pair's SiLU, so the matrix cores and
+// the vector ALUs of one wavefront work at the same time.  Activation units:
+// 16 packs (point tile nt, register r: two SiLU values -> two bfloat16), the
+// lane swaps of a point tile after its four packs.
+template <int KS, bool ACT, bool MUL>
+__device__ __forceinline__ void stage(const __bf16 *W, int w_row, const float *bias, const u32x4 (&bin)[4][4], int j,
+                                      f32x4 (&acc0)[4], f32x4 (&acc1)[4], const f32x4 (&prev0)[4],
+                                      const f32x4 (&prev1)[4], u32x4 (&bout)[4][4], int p, int q) {
+    uint32_t pk[4][4];
+    int unit = 0;
+    auto act_units = [&](int n) {
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt) {
-        const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias + mt * 16 + 4 * q);
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = bv;
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W + (mt * 16 + p) * w_row + kk * 32 + 8 * q);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf16x8(b[kk][nt]), acc[mt][nt], 0, 0, 0);
+        for (int u = 0; u < 16; ++u) {
+            if (u < unit || u >= unit + n) continue;
+            const int nt = u >> 2, r = u & 3;
+            const f32x4 &c = (r < 2) ? prev0[nt] : prev1[nt];
+            const int e = 2 * (r & 1);
+            pk[nt][r] = pack_bf16(fast_silu(c[e]), fast_silu(c[e + 1]));
+            if (r == 3) {
+                // rows of 16 lanes: (x, y) -> ([x0 x1 y0 y1], [x2 x3 y2 y3]) -> ([x0 x2 y0 y2], [x1 x3 y1 y3])
+                const auto a0 = __builtin_amdgcn_permlane32_swap(pk[nt][0], pk[nt][2], false, false);
+                const auto b0 = __builtin_amdgcn_permlane16_swap(a0[0], a0[1], false, false);
+                const auto a1 = __builtin_amdgcn_permlane32_swap(pk[nt][1], pk[nt][3], false, false);
+                const auto b1 = __builtin_amdgcn_permlane16_swap(a1[0], a1[1], false, false);
+                bout[j - 1][nt] = u32x4{b0[0], b1[0], b0[1], b1[1]};
+            }
         }
-        // keep each tile's weight loads next to its products (no hoisting of
-        // all 32 operand loads, which would need 128 more registers)
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
-__device__ __forceinline__ void to_operands(const f32x4 (&acc)[8][4], u32x4 (&b)[4][4]) {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
+        unit += n;
+    };
+    if (MUL) {
+        const f32x4 bv0 = *reinterpret_cast<const f32x4 *>(bias + (2 * j) * 16 + 4 * q);
+        const f32x4 bv1 = *reinterpret_cast<const f32x4 *>(bias + (2 * j + 1) * 16 + 4 * q);
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            b[kk][nt] = silu_to_operand(acc[2 * kk][nt], acc[2 * kk + 1][nt]);
-            __builtin_amdgcn_sched_barrier(0);
+            acc0[nt] = bv0;
+            acc1[nt] = bv1;
         }
+    }
+    constexpr int per = 16 / (4 * KS) > 0 ? 16 / (4 * KS) : 1;   // activation units per product pair
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+        bf16x8 a0, a1;
+        if (MUL) {
+            a0 = *reinterpret_cast<const bf16x8 *>(W + ((2 * j) * 16 + p) * w_row + kk * 32 + 8 * q);
+            a1 = *reinterpret_cast<const bf16x8 *>(W + ((2 * j + 1) * 16 + p) * w_row + kk * 32 + 8 * q);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            if (MUL) {
+                acc0[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, as_bf16x8(bin[kk][nt]), acc0[nt], 0, 0, 0);
+                acc1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, as_bf16x8(bin[kk][nt]), acc1[nt], 0, 0, 0);
+            }
+            if (ACT) act_units(MUL ? per : 16);
+            if (ACT && !MUL) return;
+        }
+    }
+    if (ACT && unit < 16) act_units(16 - unit);
+}
+
+// One hidden layer, bout = SiLU(bias + W * bin) in the next layer's operand
+// layout, as four stages over pairs of output tiles; at most two pairs of
+// accumulators (64 registers) are live instead of all eight tiles.
+template <int KS>
+__device__ __forceinline__ void hidden_layer(const __bf16 *W, int w_row, const float *bias, const u32x4 (&bin)[4][4],
+                                             u32x4 (&bout)[4][4], int p, int q) {
+    f32x4 a0[4], a1[4], c0[4], c1[4];
+    stage<KS, false, true>(W, w_row, bias, bin, 0, a0, a1, c0, c1, bout, p, q);
+    __builtin_amdgcn_sched_barrier(0);
+    stage<KS, true, true>(W, w_row, bias, bin, 1, c0, c1, a0, a1, bout, p, q);
+    __builtin_amdgcn_sched_barrier(0);
+    stage<KS, true, true>(W, w_row, bias, bin, 2, a0, a1, c0, c1, bout, p, q);
+    __builtin_amdgcn_sched_barrier(0);
+    stage<KS, true, true>(W, w_row, bias, bin, 3, c0, c1, a0, a1, bout, p, q);
+    __builtin_amdgcn_sched_barrier(0);
+    stage<KS, true, false>(W, w_row, bias, bin, 4, a0, a1, c0, c1, bout, p, q);
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 // Rows of region r: [r * rcap, r * rcap + count), the count from the slot
@@ -225,14 +275,11 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
             __builtin_amdgcn_sched_barrier(0);
         }
 
-        // ---- three hidden layers -------------------------------------------
-        f32x4 acc[8][4];
-        hidden_layer<1>(W + kW1, kRow1, bias, b, acc, p, q);
-        to_operands(acc, b);
-        hidden_layer<4>(W + kW2, kRowH, bias + 128, b, acc, p, q);
-        to_operands(acc, b);
-        hidden_layer<4>(W + kW3, kRowH, bias + 256, b, acc, p, q);
-        to_operands(acc, b);
+        // ---- three hidden layers (operands alternate between b and b2) -----
+        u32x4 b2[4][4];
+        hidden_layer<1>(W + kW1, kRow1, bias, b, b2, p, q);
+        hidden_layer<4>(W + kW2, kRowH, bias + 128, b2, b, p, q);
+        hidden_layer<4>(W + kW3, kRowH, bias + 256, b, b2, p, q);
 
         // ---- output layer: 12 units (one tile), outputs 4q..4q+3 per lane ----
         f32x4 y4[4];
@@ -245,7 +292,7 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
                 const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W + kW4 + p * kRowH + kk * 32 + 8 * q);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
-                    y4[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf16x8(b[kk][nt]), y4[nt], 0, 0, 0);
+                    y4[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf16x8(b2[kk][nt]), y4[nt], 0, 0, 0);
             }
         }
 

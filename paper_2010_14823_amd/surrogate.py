@@ -39,9 +39,9 @@ def generate_samples(seeds=range(10, 20), per_seed=400_000, dt=2.0, log=print):
     n = 0
     for s in seeds:
         cfg = training_config(s)
-        f, dz, _ = synth.generate(cfg)
-        st = torch.from_numpy(synth.stack(f)).cuda()
-        del f
+        st_h, dz = synth.generate_stacked(cfg, workers=8)
+        st = torch.from_numpy(st_h).cuda()
+        del st_h
         tend = torch.empty((12, cfg.nlev, cfg.ncol), dtype=torch.float64, device="cuda")
         sfc = torch.empty((8, cfg.ncol), dtype=torch.float64, device="cuda")
         # keep probability so that about per_seed of the active points are sampled

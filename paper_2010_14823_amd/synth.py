@@ -226,17 +226,18 @@ def _rows(cfg: Config, rows, mask):
     return out
 
 
-def generate(cfg: Config, rows=None):
+def generate(cfg: Config, rows=None, mask=None):
     """Synthetic state for ``cfg`` (all rows, or the listed grid rows).
 
     Returns ``(fields, dz, cols)``: ``fields`` maps each name in ``FIELDS`` to a
     float64 array of shape (nlev, ncols); ``dz`` is (nlev,); ``cols`` holds the
-    global column indices of the generated columns.
+    global column indices of the generated columns.  ``mask`` may pass
+    ``cloud_mask(cfg)`` in when it is already known.
     """
     if rows is None:
         rows = range(cfg.ny)
     rows = list(rows)
-    mask_all = cloud_mask(cfg)
+    mask_all = cloud_mask(cfg) if mask is None else mask
     sub = np.concatenate([mask_all[y * cfg.nx:(y + 1) * cfg.nx] for y in rows]) if rows else np.zeros(0, bool)
     fields = _rows(cfg, rows, sub)
     dz, _ = vertical_grid(cfg.nlev)
@@ -247,3 +248,26 @@ def generate(cfg: Config, rows=None):
 def stack(fields) -> np.ndarray:
     """(14, nlev, ncol) contiguous array in FIELDS order."""
     return np.ascontiguousarray(np.stack([fields[f] for f in FIELDS]))
+
+
+def generate_stacked(cfg: Config, workers: int = 8, rows_per_task: int = 16):
+    """The whole (14, nlev, ncol) state of ``cfg`` in FIELDS order, filled by
+    ``workers`` threads over blocks of grid rows (bitwise what
+    ``stack(generate(cfg)[0])`` returns: every row draws from its own
+    stream).  Returns ``(state, dz)``."""
+    import concurrent.futures as cf
+    mask = cloud_mask(cfg)
+    out = np.empty((len(FIELDS), cfg.nlev, cfg.ncol), dtype=np.float64)
+
+    def task(y0):
+        rows = range(y0, min(cfg.ny, y0 + rows_per_task))
+        f, _, cols = generate(cfg, rows, mask=mask)
+        c0, c1 = cols[0], cols[-1] + 1
+        for j, name in enumerate(FIELDS):
+            out[j, :, c0:c1] = f[name]
+        return None
+
+    with cf.ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        list(ex.map(task, range(0, cfg.ny, rows_per_task)))
+    dz, _ = vertical_grid(cfg.nlev)
+    return out, dz

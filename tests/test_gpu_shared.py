@@ -1,0 +1,74 @@
+"""Several parent-model ranks sharing the one GPU (the paper's ranks share a
+GPU through MPS, Sec. III-C): four processes, each with its own library
+context and stream, step interleaved shares of the 256 x 256 x 100 domain's
+grid rows concurrently; the union of their outputs must equal the oracle on
+the whole domain to the binary64 bound, and each share must be bitwise what
+one process computes for it alone."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2010_14823_amd import synth
+from util import field_errors
+
+pytestmark = pytest.mark.gpu
+NRANKS = 4
+
+
+def _rank(rank, nranks, outdir, barrier):
+    import torch
+    from paper_2010_14823_amd import casim
+    cfg = synth.CONFIGS["c1"]
+    rows = list(range(rank, cfg.ny, nranks))
+    f, dz, cols = synth.generate(cfg, rows)
+    st = synth.stack(f)
+    dev = torch.from_numpy(st).cuda()
+    tend = torch.full((12,) + st.shape[1:], -7.0, dtype=torch.float64, device="cuda")
+    sfc = torch.full((8, st.shape[2]), -7.0, dtype=torch.float64, device="cuda")
+    casim.init()
+    barrier.wait(timeout=300)                 # all ranks step at the same time
+    for _ in range(3):
+        casim.step(dev, dz, cfg.dt, tend, sfc)
+    torch.cuda.synchronize()
+    np.save(os.path.join(outdir, "t%d.npy" % rank), tend.cpu().numpy())
+    np.save(os.path.join(outdir, "s%d.npy" % rank), sfc.cpu().numpy())
+    np.save(os.path.join(outdir, "c%d.npy" % rank), cols)
+
+
+def test_ranks_sharing_the_gpu(oracle_lib, tmp_path):
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(NRANKS)
+    procs = [ctx.Process(target=_rank, args=(r, NRANKS, str(tmp_path), barrier)) for r in range(NRANKS)]
+    for p in procs:
+        p.start()
+    for p in procs:
+        p.join(timeout=300)
+    assert all(p.exitcode == 0 for p in procs), [p.exitcode for p in procs]
+    cfg = synth.CONFIGS["c1"]
+    tend = np.full((12, cfg.nlev, cfg.ncol), np.nan)
+    sfc = np.full((8, cfg.ncol), np.nan)
+    for r in range(NRANKS):
+        cols = np.load(tmp_path / ("c%d.npy" % r))
+        tend[:, :, cols] = np.load(tmp_path / ("t%d.npy" % r))
+        sfc[:, cols] = np.load(tmp_path / ("s%d.npy" % r))
+    assert not np.isnan(tend).any() and not np.isnan(sfc).any()
+    f, dz, _ = synth.generate(cfg)
+    st = synth.stack(f)
+    to, so = oracle_lib.step(st, dz, cfg.dt)
+    errs = field_errors(tend, sfc, to, so)
+    print("%d ranks on one GPU: worst normwise error %.3g" % (NRANKS, max(errs.values())))
+    assert max(errs.values()) <= 1e-12, errs
+    # a share stepped by this process alone gives bitwise the same answer
+    import torch
+    from paper_2010_14823_amd import casim
+    rows = list(range(1, cfg.ny, NRANKS))
+    g, _, cols = synth.generate(cfg, rows)
+    dev = torch.from_numpy(synth.stack(g)).cuda()
+    t1 = torch.empty((12, cfg.nlev, len(cols)), dtype=torch.float64, device="cuda")
+    s1 = torch.empty((8, len(cols)), dtype=torch.float64, device="cuda")
+    casim.init()
+    casim.step(dev, dz, cfg.dt, t1, s1)
+    torch.cuda.synchronize()
+    assert np.array_equal(t1.cpu().numpy(), tend[:, :, cols]) and np.array_equal(s1.cpu().numpy(), sfc[:, cols])

@@ -236,7 +236,7 @@ def test_trained_network_beats_untrained_and_zero():
     m = tr.m.cpu().numpy()[tr.val_idx]
     y0 = -np.array(tr.stats.y_mean) / np.array(tr.stats.y_std)
     zero = float(np.sum(m * (y0 - y) ** 2) / np.sum(m))
-    hist = tr.fit(epochs=4, batch=2048, lr=2e-3)
+    hist = tr.fit(epochs=10, batch=2048, lr=2e-3)
     trained = hist[-1]["val_loss"]
     print("validation loss: untrained %.4f, zero predictor %.4f, trained %.4f" % (untrained, zero, trained))
     assert trained < 0.2 * untrained
