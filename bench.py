@@ -477,6 +477,19 @@ def main():
     t64 = time_steps(torch, casim, dev, dz, c3.dt, tend, sfc, K, W)
     log("fp64 %s: %.4f ms/step (events: median %.4f)" % (c3.name, t64["ms_per_step"], t64["event_ms"]["median"]))
     ref_t, ref_s = tend.clone(), sfc.clone()
+    # the step's own memory traffic without its physics (same tiles, order,
+    # activity test and loads; zeros stored): its streaming floor
+    stream = torch.cuda.current_stream()
+    for _ in range(W):
+        casim.debug_stream(dev, dz, c3.dt, tend, sfc)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for a, b in ev:
+        a.record(stream)
+        casim.debug_stream(dev, dz, c3.dt, tend, sfc)
+        b.record(stream)
+    torch.cuda.synchronize()
+    floor_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    log("streaming floor of the step's access pattern: %.4f ms" % floor_ms)
     casim.init(casim.default_constants(mode=1))
     t32 = time_steps(torch, casim, dev, dz, c3.dt, tend, sfc, K, W)
     log("fp32mix %s: %.4f ms/step" % (c3.name, t32["ms_per_step"]))
@@ -567,6 +580,11 @@ def main():
                      "kernel": "sweep_kernel, binary64 (HIP events around each step on the launch stream; the "
                                "tile-order kernel of ~20 us that precedes it is included)",
                      "kernel_ms": kern_ms, "algorithmic_bytes": alg,
+                     "streaming_floor_ms": floor_ms,
+                     "streaming_floor_GBps": alg / (floor_ms * 1e-3) / 1e9,
+                     "frac_of_streaming_floor": floor_ms / kern_ms,
+                     "streaming_floor": "casim_debug_stream: the same sweep (tiles, launch order, activity test, "
+                                        "the loads of busy chunks) storing zeros, no physics",
                      "bytes_per_point": {"cloudy_column": B_CLOUDY, "clear_column": B_CLEAR,
                                          "per_column": B_COLUMN}},
         "modes": modes,

@@ -405,6 +405,15 @@ int casim_host_times(double *h2d_ms, double *step_ms, double *d2h_ms, int32_t *n
 int casim_host_alloc(void **p, size_t bytes);
 int casim_host_free(void *p);
 
+/* [proposal] Diagnostics: the streaming floor of casim_step's own memory
+ * traffic.  Runs the step's sweep with its tiles, launch order and activity
+ * test and makes the loads the step makes (8 fields per point, the other 6
+ * where a chunk is busy), then stores zeros as the 12 tendencies and
+ * surface values -- no physics.  Its time is what the step's bytes cost in
+ * the step's own access pattern; the outputs are meaningless.  Arguments
+ * and errors as casim_step (the mode of the context is ignored). */
+int casim_debug_stream(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream);
+
 /* [proposal] Diagnostics: evaluate the binary64 exponential and logarithm that the
  * step kernels use internally, elementwise on n device values x (x > 0 for a
  * meaningful log), into device arrays exp_out and log_out (either may be

@@ -114,6 +114,7 @@ def lib():
             "casim_finalize": [],
             "casim_nsub": [ctypes.POINTER(ctypes.c_double), i32, dbl, ctypes.POINTER(ctypes.c_int32)],
             "casim_debug_math": [vp, i64, vp, vp, vp],
+            "casim_debug_stream": [ctypes.POINTER(State), i64, i32, dbl, vp],
             "casim_rates_dump": [ctypes.POINTER(State), i64, i32, dbl, ctypes.c_uint64, dbl, i64, vp, vp, vp,
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), vp],
             "casim_mlp_fit_stats": [vp, vp, vp, i64, ctypes.POINTER(MlpStats), vp],
@@ -283,6 +284,16 @@ def nsub(dz, dt: float):
     _check(lib().casim_nsub(dzh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(dzh),
                             float(dt), out), "casim_nsub")
     return list(out)
+
+
+def debug_stream(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
+    """casim_debug_stream: the step's memory traffic without its physics."""
+    nlev, ld = state.shape[1], state.shape[2]
+    ncol = ld if ncol is None else int(ncol)
+    _check_tensors(state, tend, sfc, ncol)
+    st = make_state(state, dz, tend, sfc, ld)
+    _check(lib().casim_debug_stream(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
+           "casim_debug_stream")
 
 
 def debug_math(x, stream=None):

@@ -887,6 +887,34 @@ int casim_finalize(void) {
     return CASIM_OK;
 }
 
+int casim_debug_stream(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream) {
+    int rc = check_state(s, ncol, nlev, dt);
+    if (rc) return rc;
+    if (ncol == 0) return CASIM_OK;
+    if (!s->dz) return CASIM_EINVAL;
+    for (int f = 0; f < CASIM_NSFC; ++f)
+        if (!s->sfc[f]) return CASIM_EINVAL;
+    for (int k = 0; k < nlev; ++k)
+        if (!pos_finite(s->dz[k])) return CASIM_EINVAL;
+    SweepArgs a{};
+    fill_args(s, ncol, nlev, dt, a);
+    nsub_of(g.c, s->dz, nlev, dt, a.nsub);
+    for (int j = 0; j < 4; ++j) a.dts[j] = dt / a.nsub[j];
+    int slot = 0;
+    for (int j = 0; j < 4; ++j) {
+        a.slot0[j] = slot;
+        slot += 2 * a.nsub[j];
+    }
+    a.nslots = slot;
+    if (slot > kMaxCarrySlots) return CASIM_ECAPACITY;
+    if ((rc = upload_dz(s->dz, nlev))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    a.mode = kModeStream;
+    if ((rc = plan_tiles(s, ncol, nlev, a, st))) return rc;
+    HIP_TRY(launch_sweep(g.P, true, a, st));
+    return CASIM_OK;
+}
+
 int casim_debug_math(const double *x, int64_t n, double *exp_out, double *log_out, void *stream) {
     if (!x || n < 0) return CASIM_EINVAL;
     if (n == 0) return CASIM_OK;

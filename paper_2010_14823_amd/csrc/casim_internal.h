@@ -11,6 +11,8 @@
 namespace casim {
 
 constexpr int kWave = 64;            // CDNA wavefront width
+// SweepArgs.mode of the streaming-floor diagnostic (no public mode value)
+constexpr int kModeStream = 100;
 constexpr int kMaxCarrySlots = 64;   // 2 moments x sum of substeps over r,i,s,g
 
 // The scheme's constants with every derived quantity folded in, so the

@@ -483,7 +483,11 @@ enum { VAR_GENERIC = 0, VAR_COLD = 1, VAR_WARM = 2 };
 // Where the 12 rates of an active point come from: evaluated in the sweep
 // (SRC_PLAIN), the surrogate network's output for the point's slot
 // (SRC_NET), or the dense rate kernel's output for its slot (SRC_DENSE).
-enum { SRC_PLAIN = 0, SRC_NET = 1, SRC_DENSE = 2 };
+// SRC_STREAM is the step's memory traffic without its physics: the same
+// tiles, launch order, activity test and loads (the 6 extra fields where a
+// chunk is busy), then 12 stores of zeros per point -- the streaming floor
+// of the step's own access pattern (a diagnostic; it computes nothing).
+enum { SRC_PLAIN = 0, SRC_NET = 1, SRC_DENSE = 2, SRC_STREAM = 3 };
 
 template <bool MIX, int VAR, int C, int SRC>
 __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void sweep_kernel(DevParams Prt, SweepArgs a) {
@@ -577,6 +581,28 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
         }
         const double T_in = w.T;
         const unsigned long long bal = __ballot((int)act);
+        if constexpr (SRC == SRC_STREAM) {
+            // the loads a busy chunk makes, stores of zeros (0 * x keeps the loads)
+            double x = 0.0;
+            bool busy_col = false;
+            if (bal != 0ull) {
+                unsigned long long cb = 0;
+#pragma unroll
+                for (int gg = 0; gg < L; ++gg) cb |= (bal >> (gg * C)) & cmask;
+                busy_col = (cb >> c) & 1ull;
+                if (vp && (act || busy_col))
+                    x = cur.extra ? cur.rho + cur.nc + cur.nr + cur.ni + cur.ns + cur.ng
+                                  : a.in[2][ix] + a.in[5][ix] + a.in[7][ix] + a.in[9][ix] + a.in[11][ix] +
+                                        a.in[13][ix];
+                wave_busy = true;
+            }
+            nxt = load_ahead(k0 - L, busy_col);
+            if (vp) {
+#pragma unroll
+                for (int f = 0; f < CASIM_NTEND; ++f) stnt(a.tend[f] + ix, 0.0 * x);
+            }
+            continue;
+        }
         if (bal == 0ull && carry_cols == 0ull) {
             nxt = load_ahead(k0 - L, false);
             if (vp) {
@@ -1061,6 +1087,7 @@ hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipSt
     if (a.mode == CASIM_MODE_SURROGATE) return launch_var<false, SRC_NET>(var, C, grid, block, lds, stream, P, a);
     if (a.mode == CASIM_MODE_FP64_COMPACT)
         return launch_var<false, SRC_DENSE>(var, C, grid, block, lds, stream, P, a);
+    if (a.mode == kModeStream) return launch_c<false, VAR_COLD, SRC_STREAM>(C, grid, block, lds, stream, P, a);
     return launch_var<false, SRC_PLAIN>(var, C, grid, block, lds, stream, P, a);
 }
 

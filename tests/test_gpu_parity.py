@@ -267,3 +267,19 @@ def test_tile_order_is_a_pure_schedule(oracle_lib, mode):
         for t, s in outs[1:]:
             assert np.array_equal(t, outs[0][0]) and np.array_equal(s, outs[0][1])
         assert not np.any(outs[0][0] == -7.0)
+
+
+def test_streaming_floor_diagnostic_runs_and_stores_zeros():
+    """casim_debug_stream (the step's traffic without physics) writes every
+    tendency and surface value of the domain, all zero for finite inputs."""
+    import torch
+    from paper_2010_14823_amd import casim
+    cfg, st, dz, _ = config_state("c1", rows=list(range(0, 256, 8)))
+    dev = torch.from_numpy(st).cuda()
+    tend = torch.full((12,) + st.shape[1:], -7.0, dtype=torch.float64, device="cuda")
+    sfc = torch.full((8, st.shape[2]), -7.0, dtype=torch.float64, device="cuda")
+    casim.init()
+    for _ in range(2):
+        casim.debug_stream(dev, dz, cfg.dt, tend, sfc)
+    torch.cuda.synchronize()
+    assert bool((tend == 0.0).all()) and bool((sfc == 0.0).all())

@@ -241,3 +241,51 @@ def test_trained_network_beats_untrained_and_zero():
     print("validation loss: untrained %.4f, zero predictor %.4f, trained %.4f" % (untrained, zero, trained))
     assert trained < 0.2 * untrained
     assert trained < 0.2 * zero
+
+
+# Stated accuracy of a trained surrogate step against the plain binary64 step
+# on a held-out domain (c4's distribution, seed 4), normwise per tendency
+# field: RMS(sur - plain) / RMS(plain) and max |sur - plain| / max |plain|.
+# Training here as in the benchmark: 4 M plain-path samples of seeds 10-19,
+# 40 epochs (with 1 M samples and 12 epochs the snow-number tendency, which
+# ice autoconversion dominates, was off by an RMS of 1.2).
+SUR_RMS_BOUND = 0.15
+SUR_MAX_BOUND = 1.5
+SUR_FALLBACK_BOUND = 0.05
+
+
+def test_trained_surrogate_step_error_and_fallback():
+    torch = _torch()
+    from paper_2010_14823_amd import casim, surrogate
+    casim.init()
+    data = surrogate.generate_samples(seeds=range(10, 20), per_seed=400_000, log=lambda m: None)
+    tr = surrogate.Trainer(data, seed=0, log=lambda m: None)
+    tr.fit(epochs=40, batch=4096, lr=2e-3)
+    del data
+    casim.surrogate_load()
+    cfg, st, dz, _ = config_state("c4", rows=list(range(0, 1024, 16)))
+    dev = torch.from_numpy(st).cuda()
+    shape = (12,) + st.shape[1:]
+    t_pl = torch.empty(shape, dtype=torch.float64, device="cuda")
+    s_pl = torch.empty((8, st.shape[2]), dtype=torch.float64, device="cuda")
+    t_su, s_su = torch.empty_like(t_pl), torch.empty_like(s_pl)
+    casim.init(casim.default_constants(mode=casim.MODE_FP64))
+    casim.step(dev, dz, cfg.dt, t_pl, s_pl)
+    casim.init(casim.default_constants(mode=casim.MODE_SURROGATE))
+    casim.status()
+    casim.step(dev, dz, cfg.dt, t_su, s_su)
+    s = casim.status()
+    a, b = t_su.cpu().numpy(), t_pl.cpu().numpy()
+    report = {}
+    for j, name in enumerate(casim.TEND_NAMES):
+        d = a[j] - b[j]
+        rms_ref = np.sqrt(np.mean(b[j] ** 2))
+        report[name] = (np.sqrt(np.mean(d ** 2)) / rms_ref if rms_ref > 0 else 0.0,
+                        np.abs(d).max() / np.abs(b[j]).max() if np.abs(b[j]).max() > 0 else 0.0)
+    fb = s["fallback"] / max(1, s["fallback"] + s["inferred"])
+    print("trained surrogate vs plain (rms, max):", {k: ("%.3g" % v[0], "%.3g" % v[1]) for k, v in report.items()},
+          "fallback fraction %.4f" % fb)
+    assert s["nonfinite"] == 0
+    assert fb <= SUR_FALLBACK_BOUND
+    for k, (rms, mx) in report.items():
+        assert rms <= SUR_RMS_BOUND and mx <= SUR_MAX_BOUND, (k, rms, mx)
