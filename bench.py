@@ -44,6 +44,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-point updates/s: FP64 plain vs FP32-mixed vs MLP surrogate @ stated error"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense bf16 matrix peak
+NET_FLOP_PER_POINT = 2 * (12 * 128 + 128 * 128 + 128 * 128 + 128 * 12)   # 71,680: 35,840 multiply-adds
 KERNEL_SOURCES = ["casim_sweep.hip", "casim_internal.h", "casim_math.h", "casim_math_tables.h", "casim_defaults.h"]
 B_CLOUDY, B_CLEAR, B_COLUMN = 208, 160, 64   # algorithmic bytes per point / column
 B_CLOUDY_WARM, B_CLEAR_WARM = 160, 136       # warm configuration: no ice-phase inputs
@@ -428,6 +429,40 @@ def single_mode(args, torch, casim, synth):
     print(json.dumps(line), flush=True)
 
 
+def infer_rows(args, torch, casim):
+    """Time the surrogate's inference kernel alone (casim_surrogate_infer) on
+    N rows of seeded standard-normal features with random gates, statistics
+    fitted to the first 200,000 rows and seeded random parameters (N(0, 0.1)):
+    the kernel's cost does not depend on what the network learned."""
+    n = args.infer_rows
+    rng = np.random.default_rng(0)
+    casim.init()
+    feat = torch.from_numpy(rng.normal(size=(n, 12)).astype(np.float32)).cuda()
+    gates = torch.from_numpy(rng.integers(0, 1 << 13, n).astype(np.int16)).cuda()
+    rates = torch.zeros((n, 12), dtype=torch.float32, device="cuda")
+    fb = torch.empty((n,), dtype=torch.uint8, device="cuda")
+    m = min(n, 200_000)
+    casim.mlp_fit_stats(feat[:m], rates[:m], gates[:m], m)
+    casim.mlp_set_params(rng.normal(0.0, 0.1, casim.MLP_NPARAMS).astype(np.float32))
+    casim.surrogate_load()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        casim.surrogate_infer(feat, gates, n, rates, fb, stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        casim.surrogate_infer(feat, gates, n, rates, fb, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    med = ms[len(ms) // 2]
+    tf = n * NET_FLOP_PER_POINT / (med * 1e-3) / 1e12
+    print(json.dumps({"kernel": "surrogate_infer_kernel", "rows": n, "launches": args.steps,
+                      "ms_median": med, "ms_min": ms[0], "ms_max": ms[-1], "TFLOPs": tf,
+                      "frac_bf16_peak": tf / BF16_PEAK_TFLOPS, "fallback": int(fb.sum().item())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -446,6 +481,8 @@ def main():
     ap.add_argument("--no-shared", action="store_true", help="skip the several-ranks-on-one-GPU measurement")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the host-resident step (copy-in / step / copy-out split, c1 and c3)")
+    ap.add_argument("--infer-rows", type=int, default=0,
+                    help="time only the surrogate inference kernel on this many synthetic rows")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the column step needs no exchange between GPUs, and this benchmark "
@@ -456,6 +493,9 @@ def main():
     import torch
     from paper_2010_14823_amd import casim, synth
 
+    if args.infer_rows:
+        infer_rows(args, torch, casim)
+        return
     if args.config:
         single_mode(args, torch, casim, synth)
         return
@@ -536,8 +576,8 @@ def main():
                                                       "the same state"},
                     "inferred_points_per_step": st_s["inferred"] / K, "fallback_points_per_step": st_s["fallback"] / K,
                     "fallback_fraction_of_slotted": st_s["fallback"] / max(1, st_s["inferred"] + st_s["fallback"]),
-                    "network_flop_per_inferred_point": 71680, "training": train})
-        rec["network_flop_per_step"] = 71680 * (st_s["inferred"] + st_s["fallback"]) / K
+                    "network_flop_per_inferred_point": NET_FLOP_PER_POINT, "training": train})
+        rec["network_flop_per_step"] = NET_FLOP_PER_POINT * (st_s["inferred"] + st_s["fallback"]) / K
         modes["surrogate"] = rec
         del dev, tend, sfc, ref_t, ref_s
         torch.cuda.empty_cache()

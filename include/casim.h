@@ -263,7 +263,9 @@ typedef struct casim_mlp_stats {
     float x_mean[12], x_std[12];   /* features                               */
     float x_min[12], x_max[12];    /* training range of every feature        */
     float y_mean[12], y_std[12];   /* scaled targets over open gates         */
-    float whiten[144];             /* W, row-major and lower-triangular, with
+    float whiten[144];             /* W, row-major and lower-triangular (zeros
+                                      above the diagonal; casim_mlp_set_stats
+                                      rejects anything else with EINVAL), with
                                       W^T W = (C + 1e-9 I)^-1 for the covariance C of
                                       the standardised features (W = L^-1, L L^T the
                                       Cholesky factorisation): the squared
@@ -338,7 +340,8 @@ int casim_surrogate_load(void);
  * by sur_range_margin of the range on each side, where the squared
  * Mahalanobis distance |W z|^2 exceeds the threshold (sur_maha_max, or the
  * training 99.9th percentile when that is 0), or where a rate comes out
- * non-finite. */
+ * non-finite.  feat (n x 12) and rates are device pointers aligned to 16
+ * bytes (rows are read and written as 16-byte vectors); EINVAL otherwise. */
 int casim_surrogate_infer(const float *feat, const uint16_t *gates, int64_t n, float *rates,
                           uint8_t *fallback, void *stream);
 

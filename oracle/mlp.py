@@ -116,14 +116,25 @@ def bf16_round(x):
 
 def forward_bf16(theta, X):
     """Inference with bfloat16 weights and activations and float32
-    accumulation: every layer input and every weight is rounded to bfloat16,
-    products and sums are formed in float32."""
-    a = bf16_round(np.asarray(X, dtype=np.float32))
-    for i, (W, b) in enumerate(unpack(np.asarray(theta, dtype=np.float64))):
+    accumulation, with the activations carried scaled by s = -log2(e) (the
+    base-2 exponent of the logistic function): with z_l = a_{l-1} W_l + b_l
+    and silu(z) = z / (1 + e^-z),
+
+        c_0 = bf16(s x),
+        u_l = c_{l-1} bf16(W_l) + s b_l   (= s z_l up to rounding),
+        c_l = bf16(u_l / (1 + 2^u_l))     (= s silu(z_l), as 2^(s z) = e^-z),
+        y   = -ln(2) (c_3 bf16(W_4) + s b_4)   (= z_4, as -ln(2) s = 1).
+
+    Every layer input and every weight is rounded to bfloat16; products,
+    sums and the scalings are formed in float32."""
+    s = np.float32(-1.4426950408889634)
+    c = bf16_round(s * np.asarray(X, dtype=np.float32))
+    layers = unpack(np.asarray(theta, dtype=np.float64))
+    for i, (W, b) in enumerate(layers):
         Wb = bf16_round(W.astype(np.float32))
-        z = (a.astype(np.float32) @ Wb).astype(np.float32) + b.astype(np.float32)
+        u = (c.astype(np.float32) @ Wb).astype(np.float32) + s * b.astype(np.float32)
         if i < 3:
-            a = bf16_round(z / (np.float32(1.0) + np.exp(-z)))
+            with np.errstate(over="ignore"):          # 2^u = inf gives c = 0
+                c = bf16_round(u / (np.float32(1.0) + np.exp2(u)))
         else:
-            a = z
-    return a
+            return np.float32(-0.6931471805599453) * u

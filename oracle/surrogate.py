@@ -122,7 +122,8 @@ def fit_stats(feat, rates, gates):
     cov = z.T @ z / max(n - 1, 1)
     st["cov"] = cov
     st["cov_inv"] = np.linalg.inv(cov + 1e-9 * np.eye(12))
-    st["whiten"] = np.linalg.inv(np.linalg.cholesky(cov + 1e-9 * np.eye(12)))
+    # W = L^-1 is lower triangular like L; np.tril keeps its zeros exact
+    st["whiten"] = np.tril(np.linalg.inv(np.linalg.cholesky(cov + 1e-9 * np.eye(12))))
     d2 = maha2(z, st["cov_inv"])
     k = int(math.ceil(0.999 * n))
     st["maha_q999"] = float(np.sort(d2)[k - 1])

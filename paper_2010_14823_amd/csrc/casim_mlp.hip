@@ -513,6 +513,9 @@ int casim_mlp_set_stats(const casim_mlp_stats *st) {
     if (!st) return CASIM_EINVAL;
     for (int j = 0; j < 12; ++j)
         if (!(st->x_std[j] > 0.0f) || !(st->y_std[j] > 0.0f)) return CASIM_EINVAL;
+    for (int i = 0; i < 12; ++i)            // the whitening factor is lower triangular
+        for (int j = i + 1; j < 12; ++j)
+            if (st->whiten[i * 12 + j] != 0.0f) return CASIM_EINVAL;
     MLP_TRY(ensure_alloc());
     MLP_TRY(hipDeviceSynchronize());
     M.stats = *st;

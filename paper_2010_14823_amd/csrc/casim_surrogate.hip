@@ -11,14 +11,16 @@
 // operand (row = output unit; W^T rows with 8 bfloat16 of padding against
 // bank conflicts, resident in LDS for the whole block) and the activations
 // the B operand (k = input unit, column = point).  The accumulator of output
-// tiles 2kk and 2kk+1 then holds, per lane, 4 consecutive units of one point,
-// and the next layer's B operand for K-step kk needs 8 consecutive units of
-// that point: after SiLU and packing to bfloat16 pairs, one
-// v_permlane32_swap and one v_permlane16_swap per 32-bit register move the
-// values to the lanes that need them (lane layout of both swaps checked on
-// the device by a probe).  Activations therefore never leave the registers,
-// LDS holds only the weights, biases and feature statistics, and a block runs
-// 8 wavefronts (2 per SIMD).  Per point the kernel also standardises the
+// tiles 2kk and 2kk+1 then holds, per lane, units 32kk + 4q .. +4 and
+// 32kk + 16 + 4q .. +4 of one point (q = lane / 16), and the next layer's B
+// operand for K-step kk needs 8 of that point's units at k = 8q .. +8: the
+// K order of the next layer's weights is permuted once, when they are
+// loaded, so that k = 32kk + 8q + 4h + i is unit 32kk + 16h + 4q + i.  The
+// SiLU values, packed to bfloat16 pairs, are then already the operand and
+// never move between lanes.  Activations never leave the registers, LDS
+// holds only the weights, biases and feature statistics, and a block runs
+// 8 wavefronts (2 per SIMD).
+// Per point the kernel also standardises the
 // features, checks them against the training range and computes the squared
 // Mahalanobis distance |W z|^2 (rows split over the 4 lanes of a point,
 // summed with two cross-lane exchanges), and after the last layer undoes the target
@@ -55,9 +57,17 @@ constexpr size_t kInferLds = (size_t)kWElems * 2 + (size_t)(kBias + kStatF) * si
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float fast_silu(float z) {
-    // z * sigma(z), sigma via the hardware base-2 exponential and reciprocal
-    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896341f * z));
+// Activations are carried scaled by s = -log2(e), the base-2 exponent of the
+// logistic function: the layer input is bfloat16(s x), the biases in LDS are
+// s b, so every accumulator comes out as u = s z, and the next layer's input
+// is s silu(z) = u / (1 + 2^u) -- one base-2 exponential, one reciprocal and
+// one product, with no scaling of z.  The output layer's accumulator s y is
+// multiplied by -ln 2 = 1/s.
+constexpr float kNegLog2e = -1.44269504088896341f;
+constexpr float kNegLn2 = -0.693147180559945309f;
+
+__device__ __forceinline__ float scaled_silu(float u) {
+    return u * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u));
 }
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -69,103 +79,88 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
 }
 
-// SiLU of output tiles 2kk, 2kk+1 (C layout: units 4q..4q+3 of point p in
-// lane p + 16q) -> B operand of K-step kk (units 8q..8q+7 of point p).
-__device__ __forceinline__ u32x4 silu_to_operand(const f32x4 &c0, const f32x4 &c1) {
-    const uint32_t x0 = pack_bf16(fast_silu(c0[0]), fast_silu(c0[1]));
-    const uint32_t x1 = pack_bf16(fast_silu(c0[2]), fast_silu(c0[3]));
-    const uint32_t y0 = pack_bf16(fast_silu(c1[0]), fast_silu(c1[1]));
-    const uint32_t y1 = pack_bf16(fast_silu(c1[2]), fast_silu(c1[3]));
-    // rows of 16 lanes: (x, y) -> ([x0 x1 y0 y1], [x2 x3 y2 y3]) -> ([x0 x2 y0 y2], [x1 x3 y1 y3])
-    const auto a0 = __builtin_amdgcn_permlane32_swap(x0, y0, false, false);
-    const auto b0 = __builtin_amdgcn_permlane16_swap(a0[0], a0[1], false, false);
-    const auto a1 = __builtin_amdgcn_permlane32_swap(x1, y1, false, false);
-    const auto b1 = __builtin_amdgcn_permlane16_swap(a1[0], a1[1], false, false);
-    return u32x4{b0[0], b1[0], b0[1], b1[1]};
-}
-
 __device__ __forceinline__ bf16x8 as_bf16x8(const u32x4 &v) { return __builtin_bit_cast(bf16x8, v); }
 
-// One stage of a hidden layer: the products of output tiles 2j, 2j+1
-// (acc0/acc1 = bias + W(rows of those tiles) * B, four point tiles, KS
-// K-steps) written in program order together with the activation of the
-// previous pair (prev0/prev1 -> bout[j - 1]): after every product pair of a
-// K-step comes a share of the previous pair's SiLU, so the matrix cores and
-// the vector ALUs of one wavefront work at the same time.  Activation units:
-// 16 packs (point tile nt, register r: two SiLU values -> two bfloat16), the
-// lane swaps of a point tile after its four packs.
-template <int KS, bool ACT, bool MUL>
-__device__ __forceinline__ void stage(const __bf16 *W, int w_row, const float *bias, const u32x4 (&bin)[4][4], int j,
+// Units of activation work done after product group ip (ip = 4 kk + nt) of
+// a stage that spreads 16 units over its first ngroups groups.
+__host__ __device__ constexpr int units_done(int ip, int ngroups) {
+    return ngroups <= 0 ? 16 : ((ip + 1) * 16 + ngroups - 1) / ngroups < 16 ? ((ip + 1) * 16 + ngroups - 1) / ngroups : 16;
+}
+
+// Issue order of product groups IP .. END - 1 of a stage: each group's
+// NTILE MFMAs, then the vector instructions of its activation units
+// (9 each: two times exp2, add, reciprocal and product, and one pack).
+template <int NTILE, int KA, int IP, int END>
+__device__ __forceinline__ void issue_pattern() {
+    if constexpr (IP < END) {
+        constexpr int units = units_done(IP, 4 * KA) - (IP > 0 ? units_done(IP - 1, 4 * KA) : 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NTILE, 0);
+        if constexpr (units > 0) __builtin_amdgcn_sched_group_barrier(0x002, units * 9, 0);
+        issue_pattern<NTILE, KA, IP + 1, END>();
+    }
+}
+
+// One pipeline stage.  Products: NTILE output tiles (tiles NTILE jm + t of
+// the layer, 0 <= t < NTILE) over all four point tiles and KS K-steps,
+// acc = bias + W(rows of those tiles) * bin.  Activation (ACT): SiLU of the
+// previous pair of output tiles (prev0 / prev1, of this layer or of the
+// layer before) -> bout[ja], as 16 units (point tile nt, register r: two
+// SiLU values -> one bfloat16 pair), spread over the product groups of the
+// first KA K-steps so that they are written before a product of this stage
+// reads them (bin and bout may be the same array).  Program and issue order
+// interleave each group's products with its share of the activation work,
+// so the vector ALU works while the matrix core does.
+template <int KS, int NTILE, bool ACT, int KA>
+__device__ __forceinline__ void stage(const __bf16 *W, int w_row, const float *bias, const u32x4 (&bin)[4][4], int jm,
                                       f32x4 (&acc0)[4], f32x4 (&acc1)[4], const f32x4 (&prev0)[4],
-                                      const f32x4 (&prev1)[4], u32x4 (&bout)[4][4], int p, int q) {
+                                      const f32x4 (&prev1)[4], u32x4 (&bout)[4][4], int ja, int p, int q) {
     uint32_t pk[4][4];
     int unit = 0;
-    auto act_units = [&](int n) {
+    auto act_until = [&](int upto) {
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            if (u < unit || u >= unit + n) continue;
+            if (u < unit || u >= upto) continue;
             const int nt = u >> 2, r = u & 3;
             const f32x4 &c = (r < 2) ? prev0[nt] : prev1[nt];
             const int e = 2 * (r & 1);
-            pk[nt][r] = pack_bf16(fast_silu(c[e]), fast_silu(c[e + 1]));
-            if (r == 3) {
-                // rows of 16 lanes: (x, y) -> ([x0 x1 y0 y1], [x2 x3 y2 y3]) -> ([x0 x2 y0 y2], [x1 x3 y1 y3])
-                const auto a0 = __builtin_amdgcn_permlane32_swap(pk[nt][0], pk[nt][2], false, false);
-                const auto b0 = __builtin_amdgcn_permlane16_swap(a0[0], a0[1], false, false);
-                const auto a1 = __builtin_amdgcn_permlane32_swap(pk[nt][1], pk[nt][3], false, false);
-                const auto b1 = __builtin_amdgcn_permlane16_swap(a1[0], a1[1], false, false);
-                bout[j - 1][nt] = u32x4{b0[0], b1[0], b0[1], b1[1]};
-            }
+            pk[nt][r] = pack_bf16(scaled_silu(c[e]), scaled_silu(c[e + 1]));
+            // k = 8q + 4h + i of K-step ja <- unit 16h + 4q + i of the previous pair
+            if (r == 3) bout[ja][nt] = u32x4{pk[nt][0], pk[nt][1], pk[nt][2], pk[nt][3]};
         }
-        unit += n;
+        unit = upto > unit ? upto : unit;
     };
-    if (MUL) {
-        const f32x4 bv0 = *reinterpret_cast<const f32x4 *>(bias + (2 * j) * 16 + 4 * q);
-        const f32x4 bv1 = *reinterpret_cast<const f32x4 *>(bias + (2 * j + 1) * 16 + 4 * q);
+    if (NTILE > 0) {
+        // bias address formed here from an opaque zero: left to itself the
+        // compiler keeps one address register per tile and layer for the
+        // whole kernel
+        int oz;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(oz));
+        const float *bq = bias + oz + 4 * q;
+        const f32x4 bv0 = *reinterpret_cast<const f32x4 *>(bq + (NTILE * jm) * 16);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            acc0[nt] = bv0;
-            acc1[nt] = bv1;
-        }
-    }
-    constexpr int per = 16 / (4 * KS) > 0 ? 16 / (4 * KS) : 1;   // activation units per product pair
+        for (int nt = 0; nt < 4; ++nt) acc0[nt] = bv0;
+        if (NTILE > 1) {
+            const f32x4 bv1 = *reinterpret_cast<const f32x4 *>(bq + (NTILE * jm + 1) * 16);
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-        bf16x8 a0, a1;
-        if (MUL) {
-            a0 = *reinterpret_cast<const bf16x8 *>(W + ((2 * j) * 16 + p) * w_row + kk * 32 + 8 * q);
-            a1 = *reinterpret_cast<const bf16x8 *>(W + ((2 * j + 1) * 16 + p) * w_row + kk * 32 + 8 * q);
+            for (int nt = 0; nt < 4; ++nt) acc1[nt] = bv1;
         }
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            if (MUL) {
-                acc0[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, as_bf16x8(bin[kk][nt]), acc0[nt], 0, 0, 0);
-                acc1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, as_bf16x8(bin[kk][nt]), acc1[nt], 0, 0, 0);
+        for (int kk = 0; kk < KS; ++kk) {
+            const bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(W + ((NTILE * jm) * 16 + p) * w_row + kk * 32 + 8 * q);
+            bf16x8 w1;
+            if (NTILE > 1)
+                w1 = *reinterpret_cast<const bf16x8 *>(W + ((NTILE * jm + 1) * 16 + p) * w_row + kk * 32 + 8 * q);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                acc0[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, as_bf16x8(bin[kk][nt]), acc0[nt], 0, 0, 0);
+                if (NTILE > 1)
+                    acc1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, as_bf16x8(bin[kk][nt]), acc1[nt], 0, 0, 0);
+                if (ACT) act_until(units_done(kk * 4 + nt, 4 * KA));
             }
-            if (ACT) act_units(MUL ? per : 16);
-            if (ACT && !MUL) return;
         }
     }
-    if (ACT && unit < 16) act_units(16 - unit);
-}
-
-// One hidden layer, bout = SiLU(bias + W * bin) in the next layer's operand
-// layout, as four stages over pairs of output tiles; at most two pairs of
-// accumulators (64 registers) are live instead of all eight tiles.
-template <int KS>
-__device__ __forceinline__ void hidden_layer(const __bf16 *W, int w_row, const float *bias, const u32x4 (&bin)[4][4],
-                                             u32x4 (&bout)[4][4], int p, int q) {
-    f32x4 a0[4], a1[4], c0[4], c1[4];
-    stage<KS, false, true>(W, w_row, bias, bin, 0, a0, a1, c0, c1, bout, p, q);
-    __builtin_amdgcn_sched_barrier(0);
-    stage<KS, true, true>(W, w_row, bias, bin, 1, c0, c1, a0, a1, bout, p, q);
-    __builtin_amdgcn_sched_barrier(0);
-    stage<KS, true, true>(W, w_row, bias, bin, 2, a0, a1, c0, c1, bout, p, q);
-    __builtin_amdgcn_sched_barrier(0);
-    stage<KS, true, true>(W, w_row, bias, bin, 3, c0, c1, a0, a1, bout, p, q);
-    __builtin_amdgcn_sched_barrier(0);
-    stage<KS, true, false>(W, w_row, bias, bin, 4, a0, a1, c0, c1, bout, p, q);
-    __builtin_amdgcn_sched_barrier(0);
+    if (ACT) act_until(16);
+    if constexpr (ACT && NTILE > 0) issue_pattern<NTILE, KA, 0, 4 * KS>();
 }
 
 // Rows of region r: [r * rcap, r * rcap + count), the count from the slot
@@ -221,87 +216,118 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
     }
     __syncthreads();
     const float maha_max = maha[0];
+    // This lane's share of a point: features f = 4i + q (i = 0, 1, 2).  Their
+    // statistics and row p of the whitening factor at those columns stay in
+    // registers (15 values).
+    float mq[3], iq[3], loq[3], hiq[3], wq[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int f = 4 * i + q;
+        mq[i] = x_mean[f];
+        iq[i] = x_istd[f];
+        loq[i] = z_lo[f];
+        hiq[i] = z_hi[f];
+        wq[i] = p < 12 ? wht[p * 12 + f] : 0.0f;
+    }
 
     for (int64_t r = blockIdx.x; r < nreg; r += gridDim.x)
     for (int64_t t = (int64_t)wv * 64, cnt = region_rows(counters, rcap, n_all, r); t < cnt;
          t += kInferWaves * 64) {
-        // The statistics are read from LDS at their use in every tile: an
-        // opaque zero in the index keeps the compiler from hoisting all of
-        // them (some 70 values per lane) into registers for the whole loop.
-        int oz;
-        asm volatile("v_mov_b32 %0, 0" : "=v"(oz));
-        const float *xm = x_mean + oz, *xi = x_istd + oz, *zl = z_lo + oz, *zh = z_hi + oz, *wi = wht + oz;
-        // ---- inputs: point 16 nt + p of the tile, features split over q ----
+        // ---- inputs: point 16 nt + p of the tile, features 4i + q ----------
         u32x4 b[4][4];
-        bool fb[4];
+        int fb[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
+            // a tile's rows past the count read the region's last row (their
+            // results are not stored)
             const int64_t i0 = t + nt * 16 + p;
-            const bool valid = i0 < cnt;
-            const int64_t row = r * rcap + i0;
-            float z[12];
+            const int64_t row = r * rcap + (i0 < cnt ? i0 : cnt - 1);
+            const float *fr = feat + row * 12 + q;
+            float z[3];
 #pragma unroll
-            for (int j = 0; j < 12; ++j) {
-                const float x = valid ? feat[row * 12 + j] : xm[j];
-                z[j] = (x - xm[j]) * xi[j];
-            }
-            // range check of features 3q..3q+2 and rows 3q..3q+2 of W z, whose
-            // squares sum to the squared Mahalanobis distance (this lane's three
-            // features picked by q, not by a register index; W is lower
-            // triangular and its zeros above the diagonal are read as zeros)
-            bool out = false;
-            float part = 0.0f;
+            for (int i = 0; i < 3; ++i) z[i] = (fr[4 * i] - mq[i]) * iq[i];
+            // range check: the largest excess over a bound of the point's 12
+            // features (a difference of two floats is positive exactly when
+            // the first is larger), the maximum over its four lanes
+            float excess = fmaxf(fmaxf(loq[0] - z[0], z[0] - hiq[0]),
+                                 fmaxf(fmaxf(loq[1] - z[1], z[1] - hiq[1]), fmaxf(loq[2] - z[2], z[2] - hiq[2])));
+            excess = fmaxf(excess, __shfl_xor(excess, 16));
+            excess = fmaxf(excess, __shfl_xor(excess, 32));
+            // W z on the matrix cores in float32: v_mfma_f32_16x16x4_f32 takes
+            // A[row l%16][k = l/16] and B[k = l/16][col l%16] from lane l, so
+            // with k = 4i + q the lane supplies W[p][4i + q] and this point's
+            // z[4i + q], and receives rows 4q .. 4q+3 of W z (rows 12..15 are
+            // zero); their squares summed over the four lanes are the squared
+            // Mahalanobis distance.
+            f32x4 wz = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int ja = 3 * q + a;
-                const float za = q == 0 ? z[a] : q == 1 ? z[3 + a] : q == 2 ? z[6 + a] : z[9 + a];
-                out |= (za < zl[ja]) | (za > zh[ja]);
-                float s_ = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 12; ++c) s_ = fmaf(wi[ja * 12 + c], z[c], s_);
-                part = fmaf(s_, s_, part);
-            }
+            for (int i = 0; i < 3; ++i) wz = __builtin_amdgcn_mfma_f32_16x16x4f32(wq[i], z[i], wz, 0, 0, 0);
+            float part = wz[0] * wz[0];
+            part = fmaf(wz[1], wz[1], part);
+            part = fmaf(wz[2], wz[2], part);
+            part = fmaf(wz[3], wz[3], part);
             part += __shfl_xor(part, 16);
             part += __shfl_xor(part, 32);
-            const int o = (int)out;
-            const int o2 = o | __shfl_xor(o, 16);
-            const int o4 = o2 | __shfl_xor(o2, 32);
-            fb[nt] = o4 != 0 || !(part <= maha_max);
-            // B operand of layer 1: features 8q..8q+7 (12 features padded to 32)
-            float v[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = q == 0 ? z[e] : (q == 1 && e < 4) ? z[8 + e] : 0.0f;
-            b[0][nt] = u32x4{pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7])};
+            // materialised here: otherwise the compiler sinks the checks to
+            // the flag's store after the network and keeps their inputs in
+            // registers across it
+            int fbi = (excess > 0.0f || !(part <= maha_max)) ? 1 : 0;
+            asm volatile("" : "+v"(fbi));
+            fb[nt] = fbi;
+            // B operand of layer 1: k = 8q + i holds s times feature 4i + q
+            // (W1's K order is permuted to match when it is loaded), zeros
+            // at k = 8q + 3 .. 8q + 7
+            b[0][nt] = u32x4{pack_bf16(kNegLog2e * z[0], kNegLog2e * z[1]), pack_bf16(kNegLog2e * z[2], 0.0f), 0u, 0u};
             __builtin_amdgcn_sched_barrier(0);
         }
 
-        // ---- three hidden layers (operands alternate between b and b2) -----
+        // ---- network: three hidden layers and the output tile, as stages ---
+        // over pairs of output tiles (operands alternate between b and b2,
+        // accumulators between a and c).  A stage's products run beside the
+        // previous pair's activation; the stage that starts a layer runs
+        // beside the last activation of the layer before, which its products
+        // need only at their last K-step.
         u32x4 b2[4][4];
-        hidden_layer<1>(W + kW1, kRow1, bias, b, b2, p, q);
-        hidden_layer<4>(W + kW2, kRowH, bias + 128, b2, b, p, q);
-        hidden_layer<4>(W + kW3, kRowH, bias + 256, b, b2, p, q);
-
-        // ---- output layer: 12 units (one tile), outputs 4q..4q+3 per lane ----
-        f32x4 y4[4];
-        {
-            const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias + 384 + 4 * q);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) y4[nt] = bv;
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W + kW4 + p * kRowH + kk * 32 + 8 * q);
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-                    y4[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf16x8(b2[kk][nt]), y4[nt], 0, 0, 0);
-            }
-        }
+        f32x4 a0[4], a1[4], c0[4], c1[4], y4[4];
+        const __bf16 *W1 = W + kW1, *W2 = W + kW2, *W3 = W + kW3, *W4 = W + kW4;
+        stage<1, 2, false, 1>(W1, kRow1, bias, b, 0, a0, a1, c0, c1, b2, 0, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<1, 2, true, 1>(W1, kRow1, bias, b, 1, c0, c1, a0, a1, b2, 0, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<1, 2, true, 1>(W1, kRow1, bias, b, 2, a0, a1, c0, c1, b2, 1, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<1, 2, true, 1>(W1, kRow1, bias, b, 3, c0, c1, a0, a1, b2, 2, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<4, 2, true, 3>(W2, kRowH, bias + 128, b2, 0, a0, a1, c0, c1, b2, 3, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<4, 2, true, 4>(W2, kRowH, bias + 128, b2, 1, c0, c1, a0, a1, b, 0, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<4, 2, true, 4>(W2, kRowH, bias + 128, b2, 2, a0, a1, c0, c1, b, 1, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<4, 2, true, 4>(W2, kRowH, bias + 128, b2, 3, c0, c1, a0, a1, b, 2, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<4, 2, true, 3>(W3, kRowH, bias + 256, b, 0, a0, a1, c0, c1, b, 3, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<4, 2, true, 4>(W3, kRowH, bias + 256, b, 1, c0, c1, a0, a1, b2, 0, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<4, 2, true, 4>(W3, kRowH, bias + 256, b, 2, a0, a1, c0, c1, b2, 1, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        stage<4, 2, true, 4>(W3, kRowH, bias + 256, b, 3, c0, c1, a0, a1, b2, 2, p, q);
+        __builtin_amdgcn_sched_barrier(0);
+        // output layer: 12 units (one tile, outputs 4q..4q+3 per lane)
+        stage<4, 1, true, 3>(W4, kRowH, bias + 384, b2, 0, y4, a1, c0, c1, b2, 3, p, q);
+        __builtin_amdgcn_sched_barrier(0);
 
         // ---- per point: undo the scaling, gates, signs ----------------------
-        // (the four lanes of a point share p, so they take the same branches;
-        // a non-finite rate anywhere in the point sends it to the plain rates)
+        // (a non-finite rate anywhere in the point sends it to the plain rates)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            const int64_t i0 = t + nt * 16 + p;
+            // row and statistics addresses formed again from an opaque zero,
+            // not kept in registers through the network
+            int oz;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(oz));
+            const float *ym = y_mean + oz, *ys = y_std + oz;
+            const int64_t i0 = t + nt * 16 + p + oz;
             const bool valid = i0 < cnt;
             const int64_t row = r * rcap + i0;
             const unsigned gw = valid ? gates[row] : 0u;
@@ -311,12 +337,13 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int j = 4 * q + e;
-                const float yv = y4[nt][e] * y_std[j] + y_mean[j];
-                // sinh: series near 0, exponentials elsewhere
+                const float yv = (kNegLn2 * y4[nt][e]) * ys[j] + ym[j];
+                // sinh from one exponential and its reciprocal.  Near 0 the
+                // difference loses relative accuracy, but its absolute error
+                // stays about 1e-7, i.e. 1e-19 kg/kg/s after the rate scale:
+                // far below the network's own error.
                 const float ey = __builtin_amdgcn_exp2f(1.44269504088896341f * yv);
-                const float y2 = yv * yv;
-                const float sh = fabsf(yv) < 0.5f ? yv * (1.0f + y2 * (1.0f / 6.0f) * (1.0f + y2 * (1.0f / 20.0f)))
-                                                  : 0.5f * (ey - __builtin_amdgcn_rcpf(ey));
+                const float sh = 0.5f * (ey - __builtin_amdgcn_rcpf(ey));
                 float rv = (float)kRateScale * sh;
                 if (j == 3 || j == 4) {      // DEPI, DEPS: sign of the ice supersaturation
                     rv = supersat_ice ? fabsf(rv) : -fabsf(rv);
@@ -387,6 +414,16 @@ uint16_t to_bf16(float f) {
     const uint32_t lsb = (u >> 16) & 1u;
     return (uint16_t)((u + 0x7fffu + lsb) >> 16);                            // round to nearest even
 }
+// Operand position of feature f in layer 1: lane group q holds features
+// 4i + q (i = 0, 1, 2) at k = 8q + i.
+int layer1_pos(int f) { return 8 * (f & 3) + (f >> 2); }
+
+// Input unit at operand position k of a layer fed by a hidden layer:
+// k = 32kk + 8q + 4h + i holds unit 32kk + 16h + 4q + i.
+int hidden_unit_at(int k) {
+    const int kk = k >> 5, q = (k >> 3) & 3, h = (k >> 2) & 1, i = k & 3;
+    return 32 * kk + 16 * h + 4 * q + i;
+}
 }  // namespace
 
 bool surrogate_ready() { return SC.ready; }
@@ -444,20 +481,24 @@ int casim_surrogate_load(void) {
     std::vector<uint16_t> w(kWElems, 0);
     std::vector<float> b(kBias, 0.0f);
     for (int n = 0; n < 128; ++n)
-        for (int k = 0; k < 12; ++k) w[kW1 + n * kRow1 + k] = to_bf16(th[kOW1 + k * 128 + n]);
+        for (int f = 0; f < 12; ++f) w[kW1 + n * kRow1 + layer1_pos(f)] = to_bf16(th[kOW1 + f * 128 + n]);
+    // layers fed by a hidden layer: operand position k holds input unit
+    // hidden_unit_at(k), the order in which the previous layer's SiLU values
+    // come out of its accumulators
     for (int n = 0; n < 128; ++n)
         for (int k = 0; k < 128; ++k) {
-            w[kW2 + n * kRowH + k] = to_bf16(th[kOW2 + k * 128 + n]);
-            w[kW3 + n * kRowH + k] = to_bf16(th[kOW3 + k * 128 + n]);
+            const int u = hidden_unit_at(k);
+            w[kW2 + n * kRowH + k] = to_bf16(th[kOW2 + u * 128 + n]);
+            w[kW3 + n * kRowH + k] = to_bf16(th[kOW3 + u * 128 + n]);
         }
     for (int n = 0; n < 12; ++n)
-        for (int k = 0; k < 128; ++k) w[kW4 + n * kRowH + k] = to_bf16(th[kOW4 + k * 12 + n]);
+        for (int k = 0; k < 128; ++k) w[kW4 + n * kRowH + k] = to_bf16(th[kOW4 + hidden_unit_at(k) * 12 + n]);
     for (int j = 0; j < 128; ++j) {
-        b[j] = th[kOB1 + j];
-        b[128 + j] = th[kOB2 + j];
-        b[256 + j] = th[kOB3 + j];
+        b[j] = kNegLog2e * th[kOB1 + j];           // biases scaled like the activations
+        b[128 + j] = kNegLog2e * th[kOB2 + j];
+        b[256 + j] = kNegLog2e * th[kOB3 + j];
     }
-    for (int j = 0; j < 12; ++j) b[384 + j] = th[kOB4 + j];
+    for (int j = 0; j < 12; ++j) b[384 + j] = kNegLog2e * th[kOB4 + j];
     if ((e = hipMemcpy(SC.w, w.data(), w.size() * 2, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(SC.bias, b.data(), b.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(SC.stats, st, sizeof *st, hipMemcpyHostToDevice)) != hipSuccess)
@@ -469,6 +510,7 @@ int casim_surrogate_load(void) {
 int casim_surrogate_infer(const float *feat, const uint16_t *gates, int64_t n, float *rates, uint8_t *fallback,
                           void *stream) {
     if (!feat || !gates || !rates || !fallback || n < 0) return CASIM_EINVAL;
+    if (((uintptr_t)feat | (uintptr_t)rates) & 15u) return CASIM_EINVAL;   // 16-byte row vectors
     if (!SC.ready) return CASIM_ENOSURROGATE;
     if (n == 0) return CASIM_OK;
     casim_thresholds t;

@@ -73,3 +73,25 @@ def test_dz_must_match_the_level_count():
             casim.make_state(state, dz, tend, sfc)
     with pytest.raises(ValueError):
         casim.step_host(np.zeros((14, 3, 4)), [10.0, 10.0], 2.0, np.zeros((12, 3, 4)), np.zeros((8, 4)))
+
+
+def test_surrogate_infer_rejects_misaligned_rows(L):
+    """Feature and rate rows are read and written as 16-byte vectors: a
+    pointer off that alignment is refused before anything is launched."""
+    vp = ctypes.c_void_p
+    ok, bad = vp(0x100000), vp(0x100004)
+    assert L.casim_surrogate_infer(bad, ok, 64, ok, ok, None) == -1
+    assert L.casim_surrogate_infer(ok, ok, 64, bad, ok, None) == -1
+
+
+def test_set_stats_rejects_a_whitening_factor_that_is_not_lower_triangular(L):
+    """The inference kernel forms each row of W z from the row's entries on
+    and below the diagonal only: statistics with anything above it are
+    refused before they reach the device."""
+    st = casim.MlpStats()
+    for j in range(12):
+        st.x_std[j] = 1.0
+        st.y_std[j] = 1.0
+        st.whiten[13 * j] = 1.0
+    st.whiten[1] = 0.5                           # row 0, column 1
+    assert L.casim_mlp_set_stats(ctypes.byref(st)) == -1
