@@ -162,6 +162,27 @@ def copy_probe(torch, nbytes=2 << 30, reps=5):
     return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms, "GBps": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def stream_ceiling(torch, casim, nbytes=2 << 30, reps=5):
+    """The library's hand-written streaming kernels (16-byte non-temporal
+    accesses) on 2 GiB: copy (bytes read + written), read-only, write-only."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    out = {"bytes": nbytes}
+    for kind, name, moved in ((0, "copy", 2 * nbytes), (1, "read", nbytes), (2, "write", nbytes)):
+        casim.debug_bandwidth(src, dst, nbytes, kind, stream)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        for _ in range(reps):
+            casim.debug_bandwidth(src, dst, nbytes, kind, stream)
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        out[name + "_GBps"] = moved / (ms * 1e-3) / 1e9
+    del src, dst
+    return out
+
+
 def time_steps(torch, casim, dev, dz, dt, tend, sfc, steps, warmup):
     """W untimed steps, then exactly K steps between two synchronisations:
     wall-clock ms per step, and per-step HIP-event times on the launch
@@ -643,6 +664,8 @@ def main():
     if not args.no_copy:
         line["copy_probe"] = copy_probe(torch)
         line["roofline"]["frac_of_copy"] = achieved / line["copy_probe"]["GBps"]
+        line["stream_ceiling"] = stream_ceiling(torch, casim)
+        line["roofline"]["frac_of_stream_copy"] = achieved / line["stream_ceiling"]["copy_GBps"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(c3, list(range(0, 64)))
     line["bench_seconds"] = time.perf_counter() - t_begin
