@@ -84,7 +84,8 @@ __device__ __forceinline__ bf16x8 as_bf16x8(const u32x4 &v) { return __builtin_b
 // Units of activation work done after product group ip (ip = 4 kk + nt) of
 // a stage that spreads 16 units over its first ngroups groups.
 __host__ __device__ constexpr int units_done(int ip, int ngroups) {
-    return ngroups <= 0 ? 16 : ((ip + 1) * 16 + ngroups - 1) / ngroups < 16 ? ((ip + 1) * 16 + ngroups - 1) / ngroups : 16;
+    const int u = ngroups <= 0 ? 16 : ((ip + 1) * 16 + ngroups - 1) / ngroups;
+    return u < 16 ? u : 16;
 }
 
 // Issue order of product groups IP .. END - 1 of a stage: each group's
