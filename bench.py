@@ -183,13 +183,15 @@ def stream_ceiling(torch, casim, nbytes=2 << 30, reps=5):
     return out
 
 
-def time_steps(torch, casim, dev, dz, dt, tend, sfc, steps, warmup):
+def time_steps(torch, casim, dev, dz, dt, tend, sfc, steps, warmup, fn=None):
     """W untimed steps, then exactly K steps between two synchronisations:
     wall-clock ms per step, and per-step HIP-event times on the launch
-    stream (median, min, max, mean)."""
+    stream (median, min, max, mean).  fn replaces casim.step (same
+    arguments), e.g. by the streaming-floor diagnostic."""
+    step = fn or casim.step
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        casim.step(dev, dz, dt, tend, sfc)
+        step(dev, dz, dt, tend, sfc)
     torch.cuda.synchronize()
     casim.status()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
@@ -197,7 +199,7 @@ def time_steps(torch, casim, dev, dz, dt, tend, sfc, steps, warmup):
     t0 = time.perf_counter()
     for a, b in ev:
         a.record(stream)
-        casim.step(dev, dz, dt, tend, sfc)
+        step(dev, dz, dt, tend, sfc)
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -424,7 +426,8 @@ def single_mode(args, torch, casim, synth):
     mask = synth.cloud_mask(cfg)
     tend = torch.empty((12, cfg.nlev, cfg.ncol), dtype=torch.float64, device="cuda")
     sfc = torch.empty((8, cfg.ncol), dtype=torch.float64, device="cuda")
-    mode = MODES[args.mode]
+    # "stream": the step's streaming floor (casim_debug_stream), no physics
+    mode = MODES.get(args.mode, 0)
     if mode == 2:
         if not args.checkpoint:
             print("--mode surrogate needs --checkpoint (or run the default benchmark, which trains one)",
@@ -434,7 +437,8 @@ def single_mode(args, torch, casim, synth):
         casim.mlp_load(open(args.checkpoint, "rb").read())
         casim.surrogate_load()
     casim.init(casim.default_constants(mode=mode, warm=1 if args.warm else 0))
-    t = time_steps(torch, casim, dev, dz, cfg.dt, tend, sfc, args.steps, args.warmup)
+    t = time_steps(torch, casim, dev, dz, cfg.dt, tend, sfc, args.steps, args.warmup,
+                   casim.debug_stream if args.mode == "stream" else None)
     rec = mode_record(cfg, mask, t, args.warm)
     pts = cfg.ncol * cfg.nlev
     line = {"metric": METRIC, "value": pts / (t["ms_per_step"] * 1e-3), "unit": "grid-point updates/s",
@@ -490,7 +494,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default=None, help="time one configuration only (c0..c4)")
-    ap.add_argument("--mode", default="fp64", choices=sorted(MODES))
+    ap.add_argument("--mode", default="fp64", choices=sorted(MODES) + ["stream"])
     ap.add_argument("--warm", action="store_true", help="warm configuration (with --config)")
     ap.add_argument("--checkpoint", default=None, help="surrogate checkpoint for --config ... --mode surrogate")
     ap.add_argument("--epochs", type=int, default=40, help="surrogate training budget in epochs")
