@@ -418,14 +418,17 @@ int casim_host_free(void *p);
 int casim_debug_stream(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream);
 
 /* [proposal] Diagnostics: the device's streaming ceiling, from hand-written
- * kernels with 16-byte non-temporal loads and stores.  kind 0 copies `bytes`
- * from src to dst; kind 1 reads src and stores one 16-byte XOR of each
- * block's words at the start of dst (the XOR of those values is the XOR of
- * all words of src); kind 2 writes zeros to dst (src unused, may be NULL).
- * src and dst are device pointers aligned to 16 bytes, dst holds `bytes`
- * bytes for every kind, bytes is a multiple of 16.  Needs no casim_init.
- * Errors: EINVAL (kind, size, NULL or misaligned pointers), EHIP. */
-int casim_debug_bandwidth(const void *src, void *dst, int64_t bytes, int32_t kind, void *stream);
+ * kernels with non-temporal loads and stores of `width` (8 or 16) bytes per
+ * lane and a grid-stride loop over `blocks` blocks of 256 threads.  kind 0
+ * copies `bytes` from src to dst; kind 1 reads src and stores one XOR of
+ * each block's words at the start of dst (the XOR of those values is the
+ * XOR of all words of src); kind 2 writes zeros to dst (src unused, may be
+ * NULL).  src and dst are device pointers aligned to `width`, dst holds
+ * `bytes` bytes for every kind, bytes is a multiple of `width`, 1 <= blocks
+ * <= 2^20.  Needs no casim_init.  Errors: EINVAL (kind, width, size, block
+ * count, NULL or misaligned pointers), EHIP. */
+int casim_debug_bandwidth(const void *src, void *dst, int64_t bytes, int32_t kind, int32_t width, int32_t blocks,
+                          void *stream);
 
 /* [proposal] Diagnostics: evaluate the binary64 exponential and logarithm that the
  * step kernels use internally, elementwise on n device values x (x > 0 for a

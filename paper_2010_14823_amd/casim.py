@@ -115,7 +115,7 @@ def lib():
             "casim_nsub": [ctypes.POINTER(ctypes.c_double), i32, dbl, ctypes.POINTER(ctypes.c_int32)],
             "casim_debug_math": [vp, i64, vp, vp, vp],
             "casim_debug_stream": [ctypes.POINTER(State), i64, i32, dbl, vp],
-            "casim_debug_bandwidth": [vp, vp, i64, i32, vp],
+            "casim_debug_bandwidth": [vp, vp, i64, i32, i32, i32, vp],
             "casim_rates_dump": [ctypes.POINTER(State), i64, i32, dbl, ctypes.c_uint64, dbl, i64, vp, vp, vp,
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), vp],
             "casim_mlp_fit_stats": [vp, vp, vp, i64, ctypes.POINTER(MlpStats), vp],
@@ -297,11 +297,12 @@ def debug_stream(state, dz, dt: float, tend, sfc, ncol: int | None = None, strea
            "casim_debug_stream")
 
 
-def debug_bandwidth(src, dst, nbytes: int, kind: int, stream=None):
+def debug_bandwidth(src, dst, nbytes: int, kind: int, width: int = 16, blocks: int = 1024, stream=None):
     """casim_debug_bandwidth: 0 copy src -> dst, 1 read src (one XOR per block
-    into dst), 2 write zeros to dst; device tensors, 16-byte aligned."""
-    _check(lib().casim_debug_bandwidth(_p(src), _p(dst), int(nbytes), int(kind), _stream_handle(stream)),
-           "casim_debug_bandwidth")
+    into dst), 2 write zeros to dst; device tensors aligned to width (8 or 16
+    bytes per lane), grid of `blocks` 256-thread blocks."""
+    _check(lib().casim_debug_bandwidth(_p(src), _p(dst), int(nbytes), int(kind), int(width), int(blocks),
+                                       _stream_handle(stream)), "casim_debug_bandwidth")
 
 
 def debug_math(x, stream=None):

@@ -98,14 +98,17 @@ def test_set_stats_rejects_a_whitening_factor_that_is_not_lower_triangular(L):
 
 
 def test_debug_bandwidth_rejects_bad_arguments(L):
-    """The streaming diagnostic checks kind, size and 16-byte alignment
+    """The streaming diagnostic checks kind, width, size, grid and alignment
     before it launches anything; an empty buffer is a no-op."""
     vp = ctypes.c_void_p
     ok, ok2, bad = vp(0x100000), vp(0x200000), vp(0x100008)
-    assert L.casim_debug_bandwidth(ok, ok2, 1024, 3, None) == -1
-    assert L.casim_debug_bandwidth(ok, ok2, 1000, 0, None) == -1
-    assert L.casim_debug_bandwidth(bad, ok2, 1024, 0, None) == -1
-    assert L.casim_debug_bandwidth(ok, bad, 1024, 2, None) == -1
-    assert L.casim_debug_bandwidth(None, ok2, 1024, 1, None) == -1
-    assert L.casim_debug_bandwidth(ok, None, 1024, 2, None) == -1
-    assert L.casim_debug_bandwidth(ok, ok2, 0, 0, None) == 0
+    assert L.casim_debug_bandwidth(ok, ok2, 1024, 3, 16, 64, None) == -1
+    assert L.casim_debug_bandwidth(ok, ok2, 1024, 0, 12, 64, None) == -1
+    assert L.casim_debug_bandwidth(ok, ok2, 1000, 0, 16, 64, None) == -1
+    assert L.casim_debug_bandwidth(ok, ok2, 1024, 0, 16, 0, None) == -1
+    assert L.casim_debug_bandwidth(ok, ok2, 1024, 0, 16, (1 << 20) + 1, None) == -1
+    assert L.casim_debug_bandwidth(bad, ok2, 1024, 0, 16, 64, None) == -1
+    assert L.casim_debug_bandwidth(ok, bad, 1024, 2, 16, 64, None) == -1
+    assert L.casim_debug_bandwidth(None, ok2, 1024, 1, 8, 64, None) == -1
+    assert L.casim_debug_bandwidth(ok, None, 1024, 2, 8, 64, None) == -1
+    assert L.casim_debug_bandwidth(ok, ok2, 0, 0, 16, 64, None) == 0
