@@ -362,14 +362,15 @@ bool tile_order_enabled() {
 struct TileHistory {
     bool valid = false;
     const void *in0 = nullptr;
-    int64_t ncol = 0, ld = 0;
+    int64_t ncol = 0, ld = 0, tiles = 0;
     int32_t nlev = 0, mode = -1, warm = -1;
-    bool same(const casim_state *s, int64_t nc, int32_t nl) const {
+    bool same(const casim_state *s, int64_t nc, int32_t nl, int64_t nt) const {
         return valid && in0 == (const void *)s->in[0] && ncol == nc && ld == s->ld && nlev == nl &&
-               mode == g.c.mode && warm == g.c.warm;
+               mode == g.c.mode && warm == g.c.warm && tiles == nt;
     }
-    void record(const casim_state *s, int64_t nc, int32_t nl) {
+    void record(const casim_state *s, int64_t nc, int32_t nl, int64_t nt) {
         valid = true; in0 = s->in[0]; ncol = nc; ld = s->ld; nlev = nl; mode = g.c.mode; warm = g.c.warm;
+        tiles = nt;
     }
 };
 
@@ -379,7 +380,7 @@ struct TileHistory {
 int plan_tiles_with(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, int32_t *busy, int32_t *order,
                     TileHistory &hist, hipStream_t st) {
     SweepGeometry geo;
-    HIP_TRY(sweep_geometry(ncol, a.nslots, &geo));
+    HIP_TRY(sweep_geometry(ncol, a.nslots, a.mode, &geo));
     TilePlan tp;
     int rc = tile_plan(geo, tp);
     if (rc) return rc;
@@ -388,11 +389,11 @@ int plan_tiles_with(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs 
     a.ntiles = geo.tiles;
     a.tile_busy = busy;
     a.order = nullptr;
-    if (hist.same(s, ncol, nlev) && tile_order_enabled()) {
+    if (hist.same(s, ncol, nlev, geo.tiles) && tile_order_enabled()) {
         HIP_TRY(launch_tile_order(busy, geo, tp.nxcd, tp.group, tp.reserve, order, st));
         a.order = order;
     }
-    hist.record(s, ncol, nlev);
+    hist.record(s, ncol, nlev, geo.tiles);
     return CASIM_OK;
 }
 
@@ -433,7 +434,7 @@ int scratch_setup(int dev) {
 
 int plan_tiles(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, hipStream_t st) {
     SweepGeometry geo;
-    HIP_TRY(sweep_geometry(ncol, a.nslots, &geo));
+    HIP_TRY(sweep_geometry(ncol, a.nslots, a.mode, &geo));
     int rc = ensure_tiles(geo.tiles);
     if (rc) return rc;
     if (!g.hist) g_hist.valid = false;
@@ -628,7 +629,7 @@ int casim_step_noalloc(const casim_state *s, int64_t ncol, int32_t nlev, double 
     a.nslots = slot;
     if (slot > kMaxCarrySlots) return CASIM_ECAPACITY;
     SweepGeometry geo;
-    HIP_TRY(sweep_geometry(ncol, a.nslots, &geo));
+    HIP_TRY(sweep_geometry(ncol, a.nslots, a.mode, &geo));
     if (geo.tiles > kNoAllocMaxTiles) return CASIM_ECAPACITY;
     hipStream_t st = (hipStream_t)stream;
     // the vertical grid goes into the scratch with the step (4 KB at most)

@@ -204,7 +204,7 @@ constexpr int kCmpState = 13;
 hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream);
 // Launch shape of the sweep for ncol columns and nslots carry slots
 // (hipErrorInvalidValue when the carries do not fit the LDS).
-hipError_t sweep_geometry(int64_t ncol, int32_t nslots, SweepGeometry *geo);
+hipError_t sweep_geometry(int64_t ncol, int32_t nslots, int mode, SweepGeometry *geo);
 // Tile launch order from the previous step's per-tile activity, separately
 // for the wavefront positions each XCD runs (see virtual_block): busy tiles
 // and most clear ones in index order, the XCD's last `reserve` clear tiles

@@ -1040,11 +1040,15 @@ hipError_t launch_var(int var, int C, dim3 grid, dim3 block, size_t lds, hipStre
 }
 
 // Columns per wavefront.  16-column tiles (16 x 4 levels, one 128-byte row
-// per level) measured best on the large domains; narrower tiles keep at
-// least 2048 wavefronts (two per SIMD) on small ones.
-int columns_per_wave(int64_t ncol) {
+// per level) measured best for the binary64 kernel on the large domains;
+// the FP32-mixed kernel, which runs at the streaming floor of its access
+// pattern, gains from 32-column tiles (256-byte rows, 2 levels per chunk)
+// on domains of at least 262,144 columns; narrower tiles keep at least 2048
+// wavefronts (two per SIMD) on small ones.
+int columns_per_wave(int64_t ncol, int mode) {
     const int forced = env_int("CASIM_COLS_PER_WAVE", 0);
     if (forced == 4 || forced == 8 || forced == 16 || forced == 32 || forced == 64) return forced;
+    if (mode == CASIM_MODE_FP32MIX && ncol / 32 >= 8192) return 32;
     if (ncol / 16 >= 2048) return 16;
     if (ncol / 8 >= 2048) return 8;
     return 4;
@@ -1052,8 +1056,8 @@ int columns_per_wave(int64_t ncol) {
 
 }  // namespace
 
-hipError_t sweep_geometry(int64_t ncol, int32_t nslots, SweepGeometry *geo) {
-    const int C = columns_per_wave(ncol);
+hipError_t sweep_geometry(int64_t ncol, int32_t nslots, int mode, SweepGeometry *geo) {
+    const int C = columns_per_wave(ncol, mode);
     // narrow tiles: enough wavefronts per block to cover whole 128-byte rows,
     // so the halves of a line are fetched by one CU
     int wpb = env_int("CASIM_WAVES_PER_BLOCK", C >= 16 ? 1 : 16 / C);
@@ -1074,7 +1078,7 @@ hipError_t sweep_geometry(int64_t ncol, int32_t nslots, SweepGeometry *geo) {
 
 hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream) {
     SweepGeometry geo;
-    const hipError_t ge = sweep_geometry(a.ncol, a.nslots, &geo);
+    const hipError_t ge = sweep_geometry(a.ncol, a.nslots, a.mode, &geo);
     if (ge != hipSuccess) return ge;
     if ((a.order || a.tile_busy) && a.ntiles != geo.tiles) return hipErrorInvalidValue;
     if (a.nxcd < 1 || a.xcd_group < 1) return hipErrorInvalidValue;
