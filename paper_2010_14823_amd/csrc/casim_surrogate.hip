@@ -1,6 +1,6 @@
 // Inference of the process-rate surrogate on the matrix cores (gfx950).
 //
-// Each wavefront evaluates the 12-128-128-128-12 SiLU network for 64 points
+// Each wavefront evaluates the 12-128-128-128-12 SiLU network for 32 points
 // with v_mfma_f32_16x16x32_bf16: bfloat16 weights and activations, float32
 // accumulation.  Operand layout of that instruction (checked on the device by
 // a probe before this kernel was written): lane l supplies A[row l%16][k =
@@ -19,7 +19,8 @@
 // SiLU values, packed to bfloat16 pairs, are then already the operand and
 // never move between lanes.  Activations never leave the registers, LDS
 // holds only the weights, biases and feature statistics, and a block runs
-// 8 wavefronts (2 per SIMD).
+// 12 wavefronts (3 per SIMD: 32 points per wavefront keep the kernel within
+// 168 registers; 64 points needed 256 and ran 2 per SIMD, 7 % slower).
 // Per point the kernel also standardises the
 // features, checks them against the training range and computes the squared
 // Mahalanobis distance |W z|^2 (rows split over the 4 lanes of a point,
@@ -48,7 +49,10 @@ constexpr int kW3 = kW2 + 128 * kRowH;
 constexpr int kW4 = kW3 + 128 * kRowH;
 constexpr int kWElems = kW4 + 16 * kRowH;               // 42,112 bfloat16 = 84,224 bytes
 constexpr int kBias = 128 * 3 + 16;
-constexpr int kInferWaves = 8;                          // two wavefronts per SIMD
+constexpr int kNT = 2;                                  // point tiles of 16 per wavefront
+constexpr int kPts = 16 * kNT;                          // points per wavefront task
+constexpr int kUnits = 4 * kNT;                         // activation units per pair of output tiles
+constexpr int kInferWaves = 12;                         // three wavefronts per SIMD
 // LDS: weights, biases, then per feature j: mean, 1/std, lower and upper
 // bound of the standardised range; per output j: target mean and std; the
 // 12 x 12 whitening factor of the feature covariance; the Mahalanobis limit.
@@ -82,10 +86,10 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 __device__ __forceinline__ bf16x8 as_bf16x8(const u32x4 &v) { return __builtin_bit_cast(bf16x8, v); }
 
 // Units of activation work done after product group ip (ip = 4 kk + nt) of
-// a stage that spreads 16 units over its first ngroups groups.
+// a stage that spreads its kUnits units over its first ngroups groups.
 __host__ __device__ constexpr int units_done(int ip, int ngroups) {
-    const int u = ngroups <= 0 ? 16 : ((ip + 1) * 16 + ngroups - 1) / ngroups;
-    return u < 16 ? u : 16;
+    const int u = ngroups <= 0 ? kUnits : ((ip + 1) * kUnits + ngroups - 1) / ngroups;
+    return u < kUnits ? u : kUnits;
 }
 
 // Issue order of product groups IP .. END - 1 of a stage: each group's
@@ -94,7 +98,7 @@ __host__ __device__ constexpr int units_done(int ip, int ngroups) {
 template <int NTILE, int KA, int IP, int END>
 __device__ __forceinline__ void issue_pattern() {
     if constexpr (IP < END) {
-        constexpr int units = units_done(IP, 4 * KA) - (IP > 0 ? units_done(IP - 1, 4 * KA) : 0);
+        constexpr int units = units_done(IP, kNT * KA) - (IP > 0 ? units_done(IP - 1, kNT * KA) : 0);
         __builtin_amdgcn_sched_group_barrier(0x008, NTILE, 0);
         if constexpr (units > 0) __builtin_amdgcn_sched_group_barrier(0x002, units * 9, 0);
         issue_pattern<NTILE, KA, IP + 1, END>();
@@ -102,24 +106,24 @@ __device__ __forceinline__ void issue_pattern() {
 }
 
 // One pipeline stage.  Products: NTILE output tiles (tiles NTILE jm + t of
-// the layer, 0 <= t < NTILE) over all four point tiles and KS K-steps,
+// the layer, 0 <= t < NTILE) over the kNT point tiles and KS K-steps,
 // acc = bias + W(rows of those tiles) * bin.  Activation (ACT): SiLU of the
 // previous pair of output tiles (prev0 / prev1, of this layer or of the
-// layer before) -> bout[ja], as 16 units (point tile nt, register r: two
+// layer before) -> bout[ja], as kUnits units (point tile nt, register r: two
 // SiLU values -> one bfloat16 pair), spread over the product groups of the
 // first KA K-steps so that they are written before a product of this stage
 // reads them (bin and bout may be the same array).  Program and issue order
 // interleave each group's products with its share of the activation work,
 // so the vector ALU works while the matrix core does.
 template <int KS, int NTILE, bool ACT, int KA>
-__device__ __forceinline__ void stage(const __bf16 *W, int w_row, const float *bias, const u32x4 (&bin)[4][4], int jm,
-                                      f32x4 (&acc0)[4], f32x4 (&acc1)[4], const f32x4 (&prev0)[4],
-                                      const f32x4 (&prev1)[4], u32x4 (&bout)[4][4], int ja, int p, int q) {
-    uint32_t pk[4][4];
+__device__ __forceinline__ void stage(const __bf16 *W, int w_row, const float *bias, const u32x4 (&bin)[4][kNT],
+                                      int jm, f32x4 (&acc0)[kNT], f32x4 (&acc1)[kNT], const f32x4 (&prev0)[kNT],
+                                      const f32x4 (&prev1)[kNT], u32x4 (&bout)[4][kNT], int ja, int p, int q) {
+    uint32_t pk[kNT][4];
     int unit = 0;
     auto act_until = [&](int upto) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < kUnits; ++u) {
             if (u < unit || u >= upto) continue;
             const int nt = u >> 2, r = u & 3;
             const f32x4 &c = (r < 2) ? prev0[nt] : prev1[nt];
@@ -139,11 +143,11 @@ __device__ __forceinline__ void stage(const __bf16 *W, int w_row, const float *b
         const float *bq = bias + oz + 4 * q;
         const f32x4 bv0 = *reinterpret_cast<const f32x4 *>(bq + (NTILE * jm) * 16);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc0[nt] = bv0;
+        for (int nt = 0; nt < kNT; ++nt) acc0[nt] = bv0;
         if (NTILE > 1) {
             const f32x4 bv1 = *reinterpret_cast<const f32x4 *>(bq + (NTILE * jm + 1) * 16);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc1[nt] = bv1;
+            for (int nt = 0; nt < kNT; ++nt) acc1[nt] = bv1;
         }
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) {
@@ -152,16 +156,16 @@ __device__ __forceinline__ void stage(const __bf16 *W, int w_row, const float *b
             if (NTILE > 1)
                 w1 = *reinterpret_cast<const bf16x8 *>(W + ((NTILE * jm + 1) * 16 + p) * w_row + kk * 32 + 8 * q);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
+            for (int nt = 0; nt < kNT; ++nt) {
                 acc0[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, as_bf16x8(bin[kk][nt]), acc0[nt], 0, 0, 0);
                 if (NTILE > 1)
                     acc1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, as_bf16x8(bin[kk][nt]), acc1[nt], 0, 0, 0);
-                if (ACT) act_until(units_done(kk * 4 + nt, 4 * KA));
+                if (ACT) act_until(units_done(kk * kNT + nt, kNT * KA));
             }
         }
     }
-    if (ACT) act_until(16);
-    if constexpr (ACT && NTILE > 0) issue_pattern<NTILE, KA, 0, 4 * KS>();
+    if (ACT) act_until(kUnits);
+    if constexpr (ACT && NTILE > 0) issue_pattern<NTILE, KA, 0, kNT * KS>();
 }
 
 // Rows of region r: [r * rcap, r * rcap + count), the count from the slot
@@ -176,7 +180,7 @@ __device__ __forceinline__ int64_t region_rows(const unsigned long long *counter
     return cnt < 0 ? 0 : (cnt > rcap ? rcap : cnt);
 }
 
-__global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__restrict__ wglob,
+__global__ __launch_bounds__(kInferWaves * 64) void surrogate_infer_kernel(const uint16_t *__restrict__ wglob,
                                                               const float *__restrict__ bias_g,
                                                               const float *__restrict__ stats_raw,
                                                               float range_margin, float maha_max_arg,
@@ -232,13 +236,13 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
     }
 
     for (int64_t r = blockIdx.x; r < nreg; r += gridDim.x)
-    for (int64_t t = (int64_t)wv * 64, cnt = region_rows(counters, rcap, n_all, r); t < cnt;
-         t += kInferWaves * 64) {
+    for (int64_t t = (int64_t)wv * kPts, cnt = region_rows(counters, rcap, n_all, r); t < cnt;
+         t += kInferWaves * kPts) {
         // ---- inputs: point 16 nt + p of the tile, features 4i + q ----------
-        u32x4 b[4][4];
-        int fb[4];
+        u32x4 b[4][kNT];
+        int fb[kNT];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
+        for (int nt = 0; nt < kNT; ++nt) {
             // a tile's rows past the count read the region's last row (their
             // results are not stored)
             const int64_t i0 = t + nt * 16 + p;
@@ -288,8 +292,8 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
         // previous pair's activation; the stage that starts a layer runs
         // beside the last activation of the layer before, which its products
         // need only at their last K-step.
-        u32x4 b2[4][4];
-        f32x4 a0[4], a1[4], c0[4], c1[4], y4[4];
+        u32x4 b2[4][kNT];
+        f32x4 a0[kNT], a1[kNT], c0[kNT], c1[kNT], y4[kNT];
         const __bf16 *W1 = W + kW1, *W2 = W + kW2, *W3 = W + kW3, *W4 = W + kW4;
         stage<1, 2, false, 1>(W1, kRow1, bias, b, 0, a0, a1, c0, c1, b2, 0, p, q);
         __builtin_amdgcn_sched_barrier(0);
@@ -322,7 +326,7 @@ __global__ __launch_bounds__(512) void surrogate_infer_kernel(const uint16_t *__
         // ---- per point: undo the scaling, gates, signs ----------------------
         // (a non-finite rate anywhere in the point sends it to the plain rates)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
+        for (int nt = 0; nt < kNT; ++nt) {
             // row and statistics addresses formed again from an opaque zero,
             // not kept in registers through the network
             int oz;
