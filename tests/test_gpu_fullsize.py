@@ -88,3 +88,42 @@ def test_largest_level_count(oracle_lib):
     assert e.value.code == -3             # CASIM_ECAPACITY
     torch.cuda.synchronize()
     assert bool((tend == -7.0).all())
+
+
+def test_fp32mix_wide_tiles_ragged_domain(oracle_lib, monkeypatch):
+    """The FP32-mixed kernel picks 32-column tiles on domains of 262,144
+    columns or more; on 521 x 509 columns (a ragged last tile) its output
+    matches the oracle on the sampled columns (last tile included) to the
+    FP32-mixed bound, and equals the 16-column tiling bit for bit (a point's
+    arithmetic does not depend on the tile shape: the flux from the level
+    above arrives by a lane shuffle or from the carry in LDS, the same
+    value either way)."""
+    import torch
+    from paper_2010_14823_amd import casim
+    cfg = synth.Config("wide_ragged", 521, 509, 20, 21, 0.5)
+    f, dz, _ = synth.generate(cfg)
+    st = synth.stack(f)
+    del f
+    ncol = st.shape[2]
+    assert ncol % 32 != 0 and ncol // 32 >= 8192
+    dev = torch.from_numpy(st).cuda()
+    idx = _sample(ncol, np.random.default_rng(5))
+    it = torch.from_numpy(idx).cuda()
+    outs = {}
+    for tiles in ("auto", "16"):
+        if tiles == "16":
+            monkeypatch.setenv("CASIM_COLS_PER_WAVE", "16")
+        tend = torch.full((12, cfg.nlev, ncol), -7.0, dtype=torch.float64, device="cuda")
+        sfc = torch.full((8, ncol), -7.0, dtype=torch.float64, device="cuda")
+        casim.init(casim.default_constants(mode=1))
+        casim.step(dev, dz, cfg.dt, tend, sfc)
+        torch.cuda.synchronize()
+        assert not bool((tend == -7.0).any()) and not bool((sfc == -7.0).any())
+        outs[tiles] = (tend.index_select(2, it).cpu().numpy(), sfc.index_select(1, it).cpu().numpy())
+        del tend, sfc
+    to, so = oracle_lib.step(np.ascontiguousarray(st[:, :, idx]), dz, cfg.dt)
+    errs = field_errors(outs["auto"][0], outs["auto"][1], to, so)
+    cross = field_errors(outs["auto"][0], outs["auto"][1], outs["16"][0], outs["16"][1])
+    print("wide ragged fp32mix: vs oracle", max(errs.values()), "32 vs 16 columns", max(cross.values()), flush=True)
+    assert max(errs.values()) <= 2e-4, errs
+    assert np.array_equal(outs["auto"][0], outs["16"][0]) and np.array_equal(outs["auto"][1], outs["16"][1]), cross
