@@ -92,7 +92,8 @@ def test_largest_level_count(oracle_lib):
 
 def test_fp32mix_wide_tiles_ragged_domain(oracle_lib, monkeypatch):
     """The FP32-mixed kernel picks 32-column tiles on domains of 262,144
-    columns or more; on 521 x 509 columns (a ragged last tile) its output
+    columns or more; on 521 x 509 columns x 21 levels (a ragged last tile,
+    a half-filled last chunk of 2 levels) its output
     matches the oracle on the sampled columns (last tile included) to the
     FP32-mixed bound, and equals the 16-column tiling bit for bit (a point's
     arithmetic does not depend on the tile shape: the flux from the level
@@ -100,7 +101,7 @@ def test_fp32mix_wide_tiles_ragged_domain(oracle_lib, monkeypatch):
     value either way)."""
     import torch
     from paper_2010_14823_amd import casim
-    cfg = synth.Config("wide_ragged", 521, 509, 20, 21, 0.5)
+    cfg = synth.Config("wide_ragged", 521, 509, 21, 21, 0.5)
     f, dz, _ = synth.generate(cfg)
     st = synth.stack(f)
     del f

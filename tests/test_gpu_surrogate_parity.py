@@ -215,8 +215,17 @@ def test_plain_rows_inference_matches_emulation(oracle_lib):
     n = len(f32)
     out = torch.empty((n, 12), dtype=torch.float32, device="cuda")
     fb = torch.empty((n,), dtype=torch.uint8, device="cuda")
-    casim.surrogate_infer(torch.from_numpy(f32).cuda(), torch.from_numpy(g.astype(np.int16)).cuda(), n, out, fb)
+    f_dev, g_dev = torch.from_numpy(f32).cuda(), torch.from_numpy(g.astype(np.int16)).cuda()
+    casim.surrogate_infer(f_dev, g_dev, n, out, fb)
     r_gpu = out.cpu().numpy().astype(np.float64)
+    # a batch smaller than one point tile gives the same rows bit for bit
+    # (each point is its own column of every product)
+    m = 7
+    out_m = torch.empty((m, 12), dtype=torch.float32, device="cuda")
+    fb_m = torch.empty((m,), dtype=torch.uint8, device="cuda")
+    casim.surrogate_infer(f_dev[:m], g_dev[:m], m, out_m, fb_m)
+    assert np.array_equal(out_m.cpu().numpy(), out.cpu().numpy()[:m])
+    assert np.array_equal(fb_m.cpu().numpy(), fb.cpu().numpy()[:m])
     thr = casim.default_thresholds()
     r_or, fb_or = osur.infer(theta, stats, f32, g, thr.sur_range_margin, stats["maha_q999"])
     near = near_boundary(osur.standardise(f32, stats), stats, thr.sur_range_margin)
