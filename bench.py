@@ -253,10 +253,26 @@ def worst(errs):
     return {"max": max(vals) if vals else 0.0, "rms": max(rms) if rms else 0.0}
 
 
-def upload(torch, synth, cfg, workers):
+def device_fields(torch, casim, host):
+    """Host fields (nf, nlev, ncol) float64 on the device in the layout the
+    library recommends: rows padded to casim_padded_ld (8 MiB + 2 KiB per
+    level row of a 1024 x 1024 domain instead of 8 MiB)."""
+    nf, nlev, ncol = host.shape
+    dev = casim.empty_fields(nf, nlev, ncol)
+    dev.copy_(torch.from_numpy(host))
+    return dev
+
+
+def outputs(torch, casim, cfg):
+    """Tendencies (padded like the state) and surface sums for cfg."""
+    return (casim.empty_fields(12, cfg.nlev, cfg.ncol),
+            torch.empty((8, cfg.ncol), dtype=torch.float64, device="cuda"))
+
+
+def upload(torch, casim, synth, cfg, workers):
     t0 = time.perf_counter()
     st, dz = synth.generate_stacked(cfg, workers=workers)
-    dev = torch.from_numpy(st).cuda()
+    dev = device_fields(torch, casim, st)
     del st
     log("%s generated and uploaded in %.1f s" % (cfg.name, time.perf_counter() - t0))
     return dev, dz
@@ -308,10 +324,11 @@ def coupled_errors(torch, casim, dev, dz, dt, nsteps=10):
     own state with the parent-model update (X += dt tend, clip at 0): per
     field error of the state after nsteps - 1 updates and of the tendencies
     of step nsteps, FP32-mixed against binary64."""
-    x64, x32 = dev.clone(), dev.clone()
-    nlev, ncol = dev.shape[1], dev.shape[2]
-    t64 = torch.empty((12, nlev, ncol), dtype=torch.float64, device="cuda")
-    t32 = torch.empty_like(t64)
+    nf, nlev, ncol = dev.shape
+    x64, x32 = casim.empty_fields(nf, nlev, ncol), casim.empty_fields(nf, nlev, ncol)
+    x64.copy_(dev)
+    x32.copy_(dev)
+    t64, t32 = casim.empty_fields(12, nlev, ncol), casim.empty_fields(12, nlev, ncol)
     s64 = torch.empty((8, ncol), dtype=torch.float64, device="cuda")
     s32 = torch.empty_like(s64)
     for s in range(nsteps):
@@ -372,9 +389,9 @@ def _shared_worker(rank, nranks, cfg_key, steps, warmup, barrier, queue):
         f, dz, _ = synth.generate(cfg, rows)
         st = synth.stack(f)
         del f
-        dev = torch.from_numpy(st).cuda()
+        dev = device_fields(torch, casim, st)
         ncol = st.shape[2]
-        tend = torch.empty((12, cfg.nlev, ncol), dtype=torch.float64, device="cuda")
+        tend = casim.empty_fields(12, cfg.nlev, ncol)
         sfc = torch.empty((8, ncol), dtype=torch.float64, device="cuda")
         casim.init()
         for _ in range(warmup):
@@ -431,10 +448,9 @@ def single_mode(args, torch, casim, synth):
     """Time one configuration in one mode (for profiling)."""
     cfg = synth.CONFIGS[args.config]
     workers = host_threads()
-    dev, dz = upload(torch, synth, cfg, workers)
+    dev, dz = upload(torch, casim, synth, cfg, workers)
     mask = synth.cloud_mask(cfg)
-    tend = torch.empty((12, cfg.nlev, cfg.ncol), dtype=torch.float64, device="cuda")
-    sfc = torch.empty((8, cfg.ncol), dtype=torch.float64, device="cuda")
+    tend, sfc = outputs(torch, casim, cfg)
     # "stream": the step's streaming floor (casim_debug_stream), no physics
     mode = MODES.get(args.mode, 0)
     if mode == 2:
@@ -542,11 +558,10 @@ def main():
     # ---- binary64 plain and FP32-mixed on the headline domain ----------------
     t0 = time.perf_counter()
     st3, dz = synth.generate_stacked(c3, workers=workers)
-    dev = torch.from_numpy(st3).cuda()
+    dev = device_fields(torch, casim, st3)
     log("%s generated and uploaded in %.1f s" % (c3.name, time.perf_counter() - t0))
     mask3 = synth.cloud_mask(c3)
-    tend = torch.empty((12, c3.nlev, c3.ncol), dtype=torch.float64, device="cuda")
-    sfc = torch.empty((8, c3.ncol), dtype=torch.float64, device="cuda")
+    tend, sfc = outputs(torch, casim, c3)
     casim.init(casim.default_constants(mode=0))
     t64 = time_steps(torch, casim, dev, dz, c3.dt, tend, sfc, K, W)
     log("fp64 %s: %.4f ms/step (events: median %.4f)" % (c3.name, t64["ms_per_step"], t64["event_ms"]["median"]))
@@ -588,10 +603,9 @@ def main():
         train = train_surrogate(torch, casim, args.epochs, args.per_seed)
         log("surrogate trained: val loss %.4f (untrained %.4f, zero predictor %.4f)"
             % (train["val_loss"], train["untrained_val_loss"], train["zero_predictor_val_loss"]))
-        dev, dz = upload(torch, synth, c4, workers)
+        dev, dz = upload(torch, casim, synth, c4, workers)
         mask4 = synth.cloud_mask(c4)
-        tend = torch.empty((12, c4.nlev, c4.ncol), dtype=torch.float64, device="cuda")
-        sfc = torch.empty((8, c4.ncol), dtype=torch.float64, device="cuda")
+        tend, sfc = outputs(torch, casim, c4)
         casim.init(casim.default_constants(mode=0))
         t64_4 = time_steps(torch, casim, dev, dz, c4.dt, tend, sfc, K, W)
         ref_t, ref_s = tend.clone(), sfc.clone()
@@ -619,9 +633,8 @@ def main():
     # ---- binary64 on the sparse deep-convection domain ---------------------------
     extra = {}
     if not args.no_c2:
-        dev, dz = upload(torch, synth, c2, workers)
-        tend = torch.empty((12, c2.nlev, c2.ncol), dtype=torch.float64, device="cuda")
-        sfc = torch.empty((8, c2.ncol), dtype=torch.float64, device="cuda")
+        dev, dz = upload(torch, casim, synth, c2, workers)
+        tend, sfc = outputs(torch, casim, c2)
         casim.init(casim.default_constants(mode=0))
         t2 = time_steps(torch, casim, dev, dz, c2.dt, tend, sfc, K, W)
         log("fp64 %s: %.4f ms/step" % (c2.name, t2["ms_per_step"]))

@@ -227,6 +227,20 @@ const char *casim_strerror(int code);
  * is this library's reading).  Host only. */
 int casim_nsub(const double *dz_host, int32_t nlev, double dt, int32_t nsub_out[4]);
 
+/* [proposal] A leading dimension for fields of ncol columns that the step
+ * streams well: ncol rounded up to a multiple of 16 (with a 128-byte aligned
+ * field base, every 16-column row segment a wavefront loads is then one
+ * aligned 128-byte line), plus 256 when the rounded count is a multiple of
+ * 512, i.e. when the row stride would be a multiple of 4 KB.  With such a
+ * stride the rows of the 4 levels and 26 fields that one wavefront reads
+ * together share all their low address bits; on 1024 x 1024 x 120 (row
+ * stride 8 MiB) that layout made the binary64 step 8 % slower (6.55 against
+ * 6.05 ms) and its streaming floor (casim_debug_stream) 20 % slower.  Any
+ * ld >= ncol stays valid; this is a recommendation for the caller's
+ * allocation.  Returns the leading dimension (0 for ncol = 0), or
+ * CASIM_EINVAL for ncol < 0 or ncol > 2^40.  Host only. */
+int64_t casim_padded_ld(int64_t ncol);
+
 /* ======================================================================
  * [proposal] Learned surrogate of the process-rate block (every entry point
  * of this section).  The paper has no learned component; this one replaces

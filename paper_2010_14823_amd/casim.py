@@ -139,6 +139,8 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
+        L.casim_padded_ld.argtypes = [i64]
+        L.casim_padded_ld.restype = ctypes.c_int64
         L.casim_strerror.argtypes = [ctypes.c_int]
         L.casim_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -206,11 +208,46 @@ def _dz_array(dz, nlev: int):
     return dzh
 
 
+def padded_ld(ncol: int) -> int:
+    """casim_padded_ld: the leading dimension the library recommends for
+    fields of ncol columns (whole 128-byte rows, and no row stride that is a
+    multiple of 4 KB)."""
+    ld = int(lib().casim_padded_ld(int(ncol)))
+    if ld < 0:
+        raise CasimError(ld, "casim_padded_ld")
+    return ld
+
+
+def empty_fields(nf: int, nlev: int, ncol: int, fill: float | None = None):
+    """Device float64 fields (nf, nlev, ncol) stored with the leading
+    dimension padded_ld(ncol): the columns view of an (nf, nlev, ld)
+    allocation.  Every entry point that takes device fields accepts such a
+    view as it is (its level stride is the leading dimension)."""
+    import torch
+    shape = (int(nf), int(nlev), padded_ld(ncol))
+    if fill is None:
+        buf = torch.empty(shape, dtype=torch.float64, device="cuda")
+    else:
+        buf = torch.full(shape, float(fill), dtype=torch.float64, device="cuda")
+    return buf[:, :, :int(ncol)]
+
+
+def _layout(state, ncol):
+    """(nlev, ld, ncol) of device fields (nf, nlev, width): ld is the level
+    stride (the width of a contiguous tensor, the padded leading dimension
+    of a view such as empty_fields returns); ncol defaults to the width."""
+    nlev, width = state.shape[1], state.shape[2]
+    ld = max(state.stride(1), width) if nlev == 1 else state.stride(1)
+    return nlev, ld, width if ncol is None else int(ncol)
+
+
 def make_state(state, dz, tend, sfc, ld: int | None = None) -> State:
     """Build a casim_state from device tensors.
 
-    ``state``: float64 cuda tensor (14, nlev, ld); ``tend``: (12, nlev, ld);
-    ``sfc``: (8, >= ncol); ``dz``: host sequence of nlev thicknesses (m).
+    ``state``: float64 cuda tensor (14, nlev, width) whose level stride is
+    the leading dimension ld (a contiguous tensor, or a view of padded
+    storage); ``tend``: (12, nlev, width) with the same ld; ``sfc``: (8, >=
+    ncol); ``dz``: host sequence of nlev thicknesses (m).
     """
     import numpy as np
     st = State()
@@ -223,27 +260,42 @@ def make_state(state, dz, tend, sfc, ld: int | None = None) -> State:
     dzh = _dz_array(dz, state.shape[1])
     st._dz_keep = dzh
     st.dz = dzh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    st.ld = int(ld if ld is not None else state.shape[-1])
+    st.ld = int(ld if ld is not None else _layout(state, None)[1])
     return st
+
+
+def _rows_ok(t, ld):
+    """t (nf, rows, width) with unit column stride, row stride ld >= width and
+    fields that do not overlap."""
+    nf, rows, width = t.shape
+    if width > 1 and t.stride(2) != 1:
+        return False
+    if rows > 1 and t.stride(1) != ld:
+        return False
+    return ld >= width and (nf <= 1 or t.stride(0) >= (rows - 1) * ld + width)
 
 
 def _check_tensors(state, tend, sfc, ncol):
     import torch
-    for name, t, lead in (("state", state, NIN), ("tend", tend, NTEND), ("sfc", sfc, NSFC)):
-        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-            raise ValueError("%s must be a contiguous float64 cuda tensor" % name)
+    for name, t, lead, dims in (("state", state, NIN, 3), ("tend", tend, NTEND, 3), ("sfc", sfc, NSFC, 2)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == dims):
+            raise ValueError("%s must be a %d-D float64 cuda tensor" % (name, dims))
         if t.shape[0] != lead:
             raise ValueError("%s must have %d fields" % (name, lead))
+    nlev, ld, _ = _layout(state, ncol)
     if state.shape[1:] != tend.shape[1:]:
-        raise ValueError("state and tend must share (nlev, ld)")
+        raise ValueError("state and tend must share (nlev, columns)")
+    if not (_rows_ok(state, ld) and _rows_ok(tend, ld)):
+        raise ValueError("state and tend need unit column stride and one level stride (the leading dimension)")
+    if not _rows_ok(sfc.unsqueeze(1), sfc.shape[1]):
+        raise ValueError("sfc needs unit column stride and non-overlapping rows")
     if sfc.shape[-1] < ncol:
         raise ValueError("sfc is shorter than ncol")
 
 
 def step(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
     """Enqueue casim_step on the current (or given) stream."""
-    nlev, ld = state.shape[1], state.shape[2]
-    ncol = ld if ncol is None else int(ncol)
+    nlev, ld, ncol = _layout(state, ncol)
     _check_tensors(state, tend, sfc, ncol)
     st = make_state(state, dz, tend, sfc, ld)
     _check(lib().casim_step(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
@@ -252,8 +304,7 @@ def step(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
 
 def step_noalloc(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
     """Enqueue casim_step_noalloc (no device allocation in the call)."""
-    nlev, ld = state.shape[1], state.shape[2]
-    ncol = ld if ncol is None else int(ncol)
+    nlev, ld, ncol = _layout(state, ncol)
     _check_tensors(state, tend, sfc, ncol)
     st = make_state(state, dz, tend, sfc, ld)
     _check(lib().casim_step_noalloc(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
@@ -261,8 +312,7 @@ def step_noalloc(state, dz, dt: float, tend, sfc, ncol: int | None = None, strea
 
 
 def apply_tendencies(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
-    nlev, ld = state.shape[1], state.shape[2]
-    ncol = ld if ncol is None else int(ncol)
+    nlev, ld, ncol = _layout(state, ncol)
     _check_tensors(state, tend, sfc, ncol)
     st = make_state(state, dz, tend, sfc, ld)
     _check(lib().casim_apply_tendencies(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
@@ -289,8 +339,7 @@ def nsub(dz, dt: float):
 
 def debug_stream(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
     """casim_debug_stream: the step's memory traffic without its physics."""
-    nlev, ld = state.shape[1], state.shape[2]
-    ncol = ld if ncol is None else int(ncol)
+    nlev, ld, ncol = _layout(state, ncol)
     _check_tensors(state, tend, sfc, ncol)
     st = make_state(state, dz, tend, sfc, ld)
     _check(lib().casim_debug_stream(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
@@ -325,8 +374,8 @@ def rates_dump(state, dz, dt, seed, keep_prob, max_samples, feat, rates, gates, 
                ncol=None, stream=None):
     """casim_rates_dump into device tensors feat (>= max x 12 float32), rates,
     gates (int16).  Returns (written, selected)."""
-    nlev, ld = state.shape[1], state.shape[2]
-    ncol = ld if ncol is None else int(ncol)
+    nlev, ld, ncol = _layout(state, ncol)
+    _check_tensors(state, tend, sfc, ncol)
     st = make_state(state, dz, tend, sfc, ld)
     n = ctypes.c_int64(0)
     sel = ctypes.c_int64(0)
@@ -410,8 +459,7 @@ def surrogate_rates(state, dz, dt, rates, flags, ncol=None, stream=None):
     """casim_surrogate_rates: per-point network rates (12, nlev, ld) float32 and
     trust-region flags (nlev, ld) uint8 of a surrogate step on ``state``."""
     import torch
-    nlev, ld = state.shape[1], state.shape[2]
-    ncol = ld if ncol is None else int(ncol)
+    nlev, ld, ncol = _layout(state, ncol)
     if not (rates.is_cuda and rates.dtype == torch.float32 and rates.is_contiguous()
             and tuple(rates.shape) == (12, nlev, ld)):
         raise ValueError("rates must be a contiguous float32 cuda tensor (12, nlev, ld)")

@@ -281,10 +281,22 @@ int ensure_timing_events(int64_t nb) {
     return CASIM_OK;
 }
 
+// The leading dimension casim_padded_ld recommends: whole 128-byte rows, and
+// no row stride that is a multiple of 4 KB (such a stride puts the rows a
+// wavefront reads together at identical low address bits, measured slower).
+int64_t padded_columns(int64_t ncol) {
+    if (ncol == 0) return 0;
+    const int64_t ld = (ncol + 15) / 16 * 16;
+    return ld % 512 == 0 ? ld + 256 : ld;
+}
+
+// Room for blocks of `ld` columns and `nlev` levels in both buffer sets,
+// whose own leading dimension is padded as casim_padded_ld recommends.
 int ensure_pipe(int64_t ld, int64_t nlev) {
     if (ld <= g.pipe_ld && nlev <= g.pipe_lev) return CASIM_OK;
     HIP_TRY(hipDeviceSynchronize());
-    const int64_t L = ld > g.pipe_ld ? ld : g.pipe_ld, K = nlev > g.pipe_lev ? nlev : g.pipe_lev;
+    const int64_t pl = padded_columns(ld);
+    const int64_t L = pl > g.pipe_ld ? pl : g.pipe_ld, K = nlev > g.pipe_lev ? nlev : g.pipe_lev;
     for (int j = 0; j < 2; ++j) {
         hipFree(g.d_pipe[j]);
         g.d_pipe[j] = nullptr;
@@ -546,6 +558,11 @@ int casim_nsub(const double *dz_host, int32_t nlev, double dt, int32_t nsub_out[
     const casim_constants c = g.init ? g.c : default_constants();
     nsub_of(c, dz_host, nlev, dt, nsub_out);
     return CASIM_OK;
+}
+
+int64_t casim_padded_ld(int64_t ncol) {
+    if (ncol < 0 || ncol > ((int64_t)1 << 40)) return CASIM_EINVAL;
+    return padded_columns(ncol);
 }
 
 int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream) {

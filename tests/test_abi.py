@@ -112,3 +112,29 @@ def test_debug_bandwidth_rejects_bad_arguments(L):
     assert L.casim_debug_bandwidth(None, ok2, 1024, 1, 8, 64, None) == -1
     assert L.casim_debug_bandwidth(ok, None, 1024, 2, 8, 64, None) == -1
     assert L.casim_debug_bandwidth(ok, ok2, 0, 0, 16, 64, None) == 0
+
+
+def test_padded_leading_dimension(L):
+    """casim_padded_ld: whole 128-byte rows, and 2 KB more where the row
+    stride would be a multiple of 4 KB; errors for sizes out of range."""
+    cases = {0: 0, 1: 16, 16: 16, 17: 32, 496: 496, 511: 512 + 256, 512: 768, 1000: 1008,
+             1 << 20: (1 << 20) + 256, 1000000: 1000000, 65536: 65536 + 256, 65536 + 16: 65536 + 16}
+    for n, want in cases.items():
+        got = casim.padded_ld(n)
+        assert got == want, (n, got, want)
+        assert got >= n and got % 16 == 0 and (got == 0 or (got * 8) % 4096 != 0)
+    for n in (-1, (1 << 40) + 1):
+        assert L.casim_padded_ld(n) == -1
+        with pytest.raises(casim.CasimError):
+            casim.padded_ld(n)
+
+
+def test_binding_rejects_field_layouts_the_abi_cannot_express():
+    """The binding checks dtype, device, field count and strides before any
+    call (CPU tensors are refused first, so this runs without a GPU)."""
+    import torch
+    x = torch.zeros((14, 3, 8), dtype=torch.float64)
+    t = torch.zeros((12, 3, 8), dtype=torch.float64)
+    s = torch.zeros((8, 8), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        casim.step(x, [1.0, 1.0, 1.0], 1.0, t, s)

@@ -2,10 +2,12 @@
 largest level count the library accepts.
 
 The 1024 x 1024 x 120 domains run whole on the GPU, as `bench.py` times them
-(16-column tiles, XCD groups of 64 blocks, and from the second step on the
-launch order built from the previous step's activity); columns are
-independent, so the oracle checks a sample of them one by one: every tenth
-tile's first column, the first and last 64 columns and 1024 random ones.
+(fields stored with the padded leading dimension casim_padded_ld gives,
+16-column tiles in binary64 and 32 in FP32-mixed, XCD groups of 64 blocks,
+and from the second step on the launch order built from the previous
+step's activity); columns are independent, so the oracle checks a sample of
+them one by one: every tenth tile's first column, the first and last 64
+columns and 1024 random ones.
 """
 import numpy as np
 import pytest
@@ -34,8 +36,12 @@ def test_full_domain_sampled_columns(oracle_lib, key, mode):
     st = synth.stack(f)
     del f
     ncol = st.shape[2]
-    dev = torch.from_numpy(st).cuda()
-    tend = torch.full((12, cfg.nlev, ncol), -7.0, dtype=torch.float64, device="cuda")
+    ld = casim.padded_ld(ncol)
+    assert ld == ncol + 256
+    dev = casim.empty_fields(14, cfg.nlev, ncol)
+    dev.copy_(torch.from_numpy(st))
+    tbuf = torch.full((12, cfg.nlev, ld), -7.0, dtype=torch.float64, device="cuda")
+    tend = tbuf[:, :, :ncol]
     sfc = torch.full((8, ncol), -7.0, dtype=torch.float64, device="cuda")
     casim.init(casim.default_constants(mode=mode))
     casim.status()
@@ -47,8 +53,10 @@ def test_full_domain_sampled_columns(oracle_lib, key, mode):
         torch.cuda.synchronize()
         outs.append((tend.index_select(2, it).cpu().numpy(), sfc.index_select(1, it).cpu().numpy()))
         assert not bool((tend == -7.0).any()) and not bool((sfc == -7.0).any())
+    # the padding columns of the leading dimension are never written
+    assert bool((tbuf[:, :, ncol:] == -7.0).all())
     status = casim.status()
-    del dev, tend, sfc
+    del dev, tend, tbuf, sfc
     torch.cuda.empty_cache()
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     to, so = oracle_lib.step(np.ascontiguousarray(st[:, :, idx]), dz, cfg.dt)

@@ -283,3 +283,46 @@ def test_streaming_floor_diagnostic_runs_and_stores_zeros():
         casim.debug_stream(dev, dz, cfg.dt, tend, sfc)
     torch.cuda.synchronize()
     assert bool((tend == 0.0).all()) and bool((sfc == 0.0).all())
+
+
+def test_padded_view_layout_matches_contiguous():
+    """Fields passed as the columns view of padded storage (level stride
+    casim_padded_ld, as `bench.py` allocates them) give the same bits as
+    contiguous fields, on a ragged column count; the padding columns are
+    neither read (NaN there stays out of every result) nor written; the
+    binding refuses views the ABI cannot express."""
+    import torch
+    from paper_2010_14823_amd import casim
+    cfg, st, dz, _ = config_state("c1", rows=list(range(0, 256, 8)))
+    ncol = 8190
+    st = np.ascontiguousarray(st[:, :, :ncol])
+    tg, sg, _, _ = run_gpu(st, dz, cfg.dt)
+    ld = casim.padded_ld(ncol)
+    assert ld == 8192 + 256
+    nlev = st.shape[1]
+    sbuf = torch.full((14, nlev, ld), float("nan"), dtype=torch.float64, device="cuda")
+    dev = sbuf[:, :, :ncol]
+    dev.copy_(torch.from_numpy(st))
+    tbuf = torch.full((12, nlev, ld), -7.0, dtype=torch.float64, device="cuda")
+    tend = tbuf[:, :, :ncol]
+    sfc = torch.full((8, ncol), -7.0, dtype=torch.float64, device="cuda")
+    casim.init()
+    casim.status()
+    casim.step(dev, dz, cfg.dt, tend, sfc)
+    torch.cuda.synchronize()
+    assert np.array_equal(tend.cpu().numpy(), tg) and np.array_equal(sfc.cpu().numpy(), sg)
+    assert bool((tbuf[:, :, ncol:] == -7.0).all())
+    # the parent-model update on the view equals the one on contiguous fields
+    ref = torch.from_numpy(st).cuda()
+    rt, rs = tend.contiguous(), sfc.clone()
+    casim.apply_tendencies(dev, dz, cfg.dt, tend, sfc)
+    casim.apply_tendencies(ref, dz, cfg.dt, rt, rs)
+    torch.cuda.synchronize()
+    assert torch.equal(dev, ref) and bool(torch.isnan(sbuf[:, :, ncol:]).all())
+    assert casim.status()["nonfinite"] == 0
+    e = casim.empty_fields(12, nlev, ncol)
+    assert tuple(e.shape) == (12, nlev, ncol) and e.stride(1) == ld
+    with pytest.raises(ValueError):       # column stride 2
+        casim.step(sbuf[:, :, 0:ncol:2], dz, cfg.dt, tbuf[:, :, 0:ncol:2], sfc)
+    with pytest.raises(ValueError):       # tendencies with another leading dimension
+        casim.step(dev, dz, cfg.dt, tend.contiguous(), sfc)

@@ -23,8 +23,9 @@ def _rank(rank, nranks, outdir, barrier):
     rows = list(range(rank, cfg.ny, nranks))
     f, dz, cols = synth.generate(cfg, rows)
     st = synth.stack(f)
-    dev = torch.from_numpy(st).cuda()
-    tend = torch.full((12,) + st.shape[1:], -7.0, dtype=torch.float64, device="cuda")
+    dev = casim.empty_fields(*st.shape)        # the layout the benchmark times
+    dev.copy_(torch.from_numpy(st))
+    tend = casim.empty_fields(12, st.shape[1], st.shape[2], fill=-7.0)
     sfc = torch.full((8, st.shape[2]), -7.0, dtype=torch.float64, device="cuda")
     casim.init()
     barrier.wait(timeout=300)                 # all ranks step at the same time

@@ -303,7 +303,8 @@ def test_surrogate_step_applies_the_network_rates(oracle_lib):
 
 def test_full_c4_sampled_columns(oracle_lib):
     """The step path on the whole 1024 x 1024 x 120 inference domain (the
-    benchmark's launch configuration); sampled columns against the oracle."""
+    benchmark's launch configuration and padded field layout); sampled
+    columns against the oracle."""
     import torch
     from paper_2010_14823_amd import casim
     cfg = synth.CONFIGS["c4"]
@@ -317,10 +318,12 @@ def test_full_c4_sampled_columns(oracle_lib):
     stats = setup_network(casim, oracle_lib, np.ascontiguousarray(st[:, :, rng.choice(ncol, 256, replace=False)]),
                           theta)
     sub = np.ascontiguousarray(st[:, :, idx])
-    dev = torch.from_numpy(st).cuda()
+    dev = casim.empty_fields(14, cfg.nlev, ncol)
+    dev.copy_(torch.from_numpy(st))
     del st
-    rates = torch.full((12, cfg.nlev, ncol), -1.0, dtype=torch.float32, device="cuda")
-    flags = torch.full((cfg.nlev, ncol), 7, dtype=torch.uint8, device="cuda")
+    ld = casim.padded_ld(ncol)
+    rates = torch.full((12, cfg.nlev, ld), -1.0, dtype=torch.float32, device="cuda")
+    flags = torch.full((cfg.nlev, ld), 7, dtype=torch.uint8, device="cuda")
     casim.surrogate_rates(dev, dz, cfg.dt, rates, flags)
     torch.cuda.synchronize()
     it = torch.from_numpy(idx).cuda()
