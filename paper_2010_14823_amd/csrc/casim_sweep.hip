@@ -429,13 +429,21 @@ __device__ __forceinline__ double limiter_min_f(const Pt &w, const double r[12],
 // ---- sedimentation of one category over one chunk --------------------------
 // Mass- and number-weighted fall speeds a Gamma(4+b)/6 lambda^-b and
 // a Gamma(1+b) lambda^-b, times (rho_0/rho)^1/2, capped at v_max.
+// carry_in: some flux of this category left the chunk above (its carries in
+// LDS are not all zero).  Returns whether some flux leaves this chunk.  With
+// no flux entering and no lane holding mass at or above q_min, every flux of
+// every substep is zero (mass moves at most one level per substep, and only
+// out of a level at or above q_min), so the chunk is skipped: its carries
+// stay the zeros they are, and q, n and the tendencies stay as they are.
 template <class R, int C>
-__device__ __forceinline__ void sediment(const DevParams &P, int cat, int ns, double dts, double *lds,
+__device__ __forceinline__ bool sediment(const DevParams &P, int cat, int ns, double dts, double *lds,
                                          int g, int c, bool need, double rho, double ln_rho, double rfac,
-                                         double inv_rdz, bool surf, double &q, double &n, double &dq,
-                                         double &dn, double *psq, double *psn, bool &out_nz) {
+                                         double inv_rdz, bool surf, bool carry_in, double &q, double &n,
+                                         double &dq, double &dn, double *psq, double *psn, bool &out_nz) {
     using M = Mth<R>;
     constexpr int L = kWave / C;
+    if (!carry_in && __ballot((int)(need && q >= P.q_min)) == 0ull) return false;
+    bool nz = false;
     double *cq = lds;                 // [s][c] flux of mass leaving the previous chunk
     double *cn = lds + ns * C;        // [s][c] flux of number
     const R ln_coef = R(P.ln_lam_coef[cat]), lo = R(P.ln_lam_lo[cat]), hi = R(P.ln_lam_hi[cat]);
@@ -469,9 +477,11 @@ __device__ __forceinline__ void sediment(const DevParams &P, int cat, int ns, do
             q += iq; dq += iq; n += in_; dn += in_;
         }
         if (g == L - 1) { cq[s * C + c] = Fq; cn[s * C + c] = Fn; }
-        out_nz |= (Fq != 0.0) | (Fn != 0.0);
+        nz |= (Fq != 0.0) | (Fn != 0.0);
         if (surf) { *psq += Fq * dts; *psn += Fn * dts; }
     }
+    out_nz |= nz;
+    return __ballot((int)(g == L - 1 && nz)) != 0ull;
 }
 
 // Kernel variants: VAR_GENERIC takes the constants and the stage/warm
@@ -523,6 +533,7 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
 
     for (int j = lane; j < (a.nslots + 8) * C; j += kWave) lds[j] = 0.0;
     unsigned long long carry_cols = 0;   // bit c: a flux enters column c's next chunk from above
+    unsigned carry_cat = 0;              // bit j: a flux of category j enters the next chunk
     const unsigned long long cmask = (C == 64) ? ~0ull : ((1ull << C) - 1ull);
     // surface sums of the wave's columns, [8][C] in LDS after the carries
     double *psurf = lds + (size_t)a.nslots * C + c;
@@ -687,16 +698,22 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
             double inv_rdz = 0.0;
             if (need) inv_rdz = rcp64(rho * a.dz[k < 0 ? 0 : k]);
             const bool surf = vp && k == 0;
-            sediment<R, C>(P, 0, a.nsub[0], a.dts[0], lds + a.slot0[0] * C, g, c, need, rho, ln_rho, rfac,
-                           inv_rdz, surf, w.qr, w.nr, d.qr, d.nr, psurf + 0 * C, psurf + 4 * C, out_nz);
+            unsigned cc = 0;
+            cc |= sediment<R, C>(P, 0, a.nsub[0], a.dts[0], lds + a.slot0[0] * C, g, c, need, rho, ln_rho,
+                                 rfac, inv_rdz, surf, carry_cat & 1u, w.qr, w.nr, d.qr, d.nr, psurf + 0 * C,
+                                 psurf + 4 * C, out_nz) ? 1u : 0u;
             if (ncat > 1) {
-                sediment<R, C>(P, 1, a.nsub[1], a.dts[1], lds + a.slot0[1] * C, g, c, need, rho, ln_rho, rfac,
-                               inv_rdz, surf, w.qi, w.ni, d.qi, d.ni, psurf + 1 * C, psurf + 5 * C, out_nz);
-                sediment<R, C>(P, 2, a.nsub[2], a.dts[2], lds + a.slot0[2] * C, g, c, need, rho, ln_rho, rfac,
-                               inv_rdz, surf, w.qs, w.ns, d.qs, d.ns, psurf + 2 * C, psurf + 6 * C, out_nz);
-                sediment<R, C>(P, 3, a.nsub[3], a.dts[3], lds + a.slot0[3] * C, g, c, need, rho, ln_rho, rfac,
-                               inv_rdz, surf, w.qg, w.ng, d.qg, d.ng, psurf + 3 * C, psurf + 7 * C, out_nz);
+                cc |= sediment<R, C>(P, 1, a.nsub[1], a.dts[1], lds + a.slot0[1] * C, g, c, need, rho, ln_rho,
+                                     rfac, inv_rdz, surf, carry_cat & 2u, w.qi, w.ni, d.qi, d.ni, psurf + 1 * C,
+                                     psurf + 5 * C, out_nz) ? 2u : 0u;
+                cc |= sediment<R, C>(P, 2, a.nsub[2], a.dts[2], lds + a.slot0[2] * C, g, c, need, rho, ln_rho,
+                                     rfac, inv_rdz, surf, carry_cat & 4u, w.qs, w.ns, d.qs, d.ns, psurf + 2 * C,
+                                     psurf + 6 * C, out_nz) ? 4u : 0u;
+                cc |= sediment<R, C>(P, 3, a.nsub[3], a.dts[3], lds + a.slot0[3] * C, g, c, need, rho, ln_rho,
+                                     rfac, inv_rdz, surf, carry_cat & 8u, w.qg, w.ng, d.qg, d.ng, psurf + 3 * C,
+                                     psurf + 7 * C, out_nz) ? 8u : 0u;
             }
+            carry_cat = cc;
         }
         carry_cols = (__ballot((int)(g == L - 1 && out_nz)) >> ((L - 1) * C)) & cmask;
         if (vp) {
