@@ -236,7 +236,7 @@ int casim_nsub(const double *dz_host, int32_t nlev, double dt, int32_t nsub_out[
  * together share all their low address bits; on 1024 x 1024 x 120 (row
  * stride 8 MiB) that layout made the binary64 step 7 % slower (6.53 against
  * 6.11 ms, median kernel time) and its streaming floor (casim_debug_stream)
- * 6-30 % slower, depending on where the buffers land.  Any
+ * 3-30 % slower, depending on where the buffers land.  Any
  * ld >= ncol stays valid; this is a recommendation for the caller's
  * allocation.  Returns the leading dimension (0 for ncol = 0), or
  * CASIM_EINVAL for ncol < 0 or ncol > 2^40.  Host only. */
