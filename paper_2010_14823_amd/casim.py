@@ -276,13 +276,14 @@ def _rows_ok(t, ld):
 
 
 def _check_tensors(state, tend, sfc, ncol):
+    """Validate device fields; returns (nlev, ld, ncol) as _layout does."""
     import torch
     for name, t, lead, dims in (("state", state, NIN, 3), ("tend", tend, NTEND, 3), ("sfc", sfc, NSFC, 2)):
-        if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == dims):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.dim() == dims):
             raise ValueError("%s must be a %d-D float64 cuda tensor" % (name, dims))
         if t.shape[0] != lead:
             raise ValueError("%s must have %d fields" % (name, lead))
-    nlev, ld, _ = _layout(state, ncol)
+    nlev, ld, ncol = _layout(state, ncol)
     if state.shape[1:] != tend.shape[1:]:
         raise ValueError("state and tend must share (nlev, columns)")
     if not (_rows_ok(state, ld) and _rows_ok(tend, ld)):
@@ -291,12 +292,12 @@ def _check_tensors(state, tend, sfc, ncol):
         raise ValueError("sfc needs unit column stride and non-overlapping rows")
     if sfc.shape[-1] < ncol:
         raise ValueError("sfc is shorter than ncol")
+    return nlev, ld, ncol
 
 
 def step(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
     """Enqueue casim_step on the current (or given) stream."""
-    nlev, ld, ncol = _layout(state, ncol)
-    _check_tensors(state, tend, sfc, ncol)
+    nlev, ld, ncol = _check_tensors(state, tend, sfc, ncol)
     st = make_state(state, dz, tend, sfc, ld)
     _check(lib().casim_step(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
            "casim_step")
@@ -304,16 +305,14 @@ def step(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
 
 def step_noalloc(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
     """Enqueue casim_step_noalloc (no device allocation in the call)."""
-    nlev, ld, ncol = _layout(state, ncol)
-    _check_tensors(state, tend, sfc, ncol)
+    nlev, ld, ncol = _check_tensors(state, tend, sfc, ncol)
     st = make_state(state, dz, tend, sfc, ld)
     _check(lib().casim_step_noalloc(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
            "casim_step_noalloc")
 
 
 def apply_tendencies(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
-    nlev, ld, ncol = _layout(state, ncol)
-    _check_tensors(state, tend, sfc, ncol)
+    nlev, ld, ncol = _check_tensors(state, tend, sfc, ncol)
     st = make_state(state, dz, tend, sfc, ld)
     _check(lib().casim_apply_tendencies(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
            "casim_apply_tendencies")
@@ -339,8 +338,7 @@ def nsub(dz, dt: float):
 
 def debug_stream(state, dz, dt: float, tend, sfc, ncol: int | None = None, stream=None):
     """casim_debug_stream: the step's memory traffic without its physics."""
-    nlev, ld, ncol = _layout(state, ncol)
-    _check_tensors(state, tend, sfc, ncol)
+    nlev, ld, ncol = _check_tensors(state, tend, sfc, ncol)
     st = make_state(state, dz, tend, sfc, ld)
     _check(lib().casim_debug_stream(ctypes.byref(st), ncol, nlev, float(dt), _stream_handle(stream)),
            "casim_debug_stream")
@@ -374,8 +372,7 @@ def rates_dump(state, dz, dt, seed, keep_prob, max_samples, feat, rates, gates, 
                ncol=None, stream=None):
     """casim_rates_dump into device tensors feat (>= max x 12 float32), rates,
     gates (int16).  Returns (written, selected)."""
-    nlev, ld, ncol = _layout(state, ncol)
-    _check_tensors(state, tend, sfc, ncol)
+    nlev, ld, ncol = _check_tensors(state, tend, sfc, ncol)
     st = make_state(state, dz, tend, sfc, ld)
     n = ctypes.c_int64(0)
     sel = ctypes.c_int64(0)
@@ -459,7 +456,12 @@ def surrogate_rates(state, dz, dt, rates, flags, ncol=None, stream=None):
     """casim_surrogate_rates: per-point network rates (12, nlev, ld) float32 and
     trust-region flags (nlev, ld) uint8 of a surrogate step on ``state``."""
     import torch
+    if not (isinstance(state, torch.Tensor) and state.is_cuda and state.dtype == torch.float64
+            and state.dim() == 3 and state.shape[0] == NIN):
+        raise ValueError("state must be a (14, nlev, columns) float64 cuda tensor")
     nlev, ld, ncol = _layout(state, ncol)
+    if not _rows_ok(state, ld):
+        raise ValueError("state needs unit column stride and one level stride (the leading dimension)")
     if not (rates.is_cuda and rates.dtype == torch.float32 and rates.is_contiguous()
             and tuple(rates.shape) == (12, nlev, ld)):
         raise ValueError("rates must be a contiguous float32 cuda tensor (12, nlev, ld)")

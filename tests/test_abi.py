@@ -138,3 +138,14 @@ def test_binding_rejects_field_layouts_the_abi_cannot_express():
     s = torch.zeros((8, 8), dtype=torch.float64)
     with pytest.raises(ValueError):
         casim.step(x, [1.0, 1.0, 1.0], 1.0, t, s)
+
+
+def test_binding_refuses_host_arrays_as_device_fields():
+    """A numpy array where device fields are expected is a ValueError, before
+    any stride is read or any call is made."""
+    x = np.zeros((14, 3, 8))
+    t = np.zeros((12, 3, 8))
+    s = np.zeros((8, 8))
+    for fn in (casim.step, casim.step_noalloc, casim.apply_tendencies, casim.debug_stream):
+        with pytest.raises(ValueError):
+            fn(x, [1.0, 1.0, 1.0], 1.0, t, s)
