@@ -356,7 +356,8 @@ int casim_surrogate_load(void);
  * Mahalanobis distance |W z|^2 exceeds the threshold (sur_maha_max, or the
  * training 99.9th percentile when that is 0), or where a rate comes out
  * non-finite.  feat (n x 12) and rates are device pointers aligned to 16
- * bytes (rows are read and written as 16-byte vectors); EINVAL otherwise. */
+ * bytes (rows are read and written as 16-byte vectors); 0 <= n <= 2^36;
+ * EINVAL otherwise. */
 int casim_surrogate_infer(const float *feat, const uint16_t *gates, int64_t n, float *rates,
                           uint8_t *fallback, void *stream);
 

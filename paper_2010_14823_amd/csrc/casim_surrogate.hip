@@ -57,9 +57,12 @@ constexpr int kUnits = 4 * kNT;                         // activation units per 
 constexpr int kInferWaves = 12;                         // three wavefronts per SIMD
 // LDS: weights, biases, then per feature j: mean, 1/std, lower and upper
 // bound of the standardised range; per output j: target mean and std; the
-// 12 x 12 whitening factor of the feature covariance; the Mahalanobis limit.
+// 12 x 12 whitening factor of the feature covariance; the Mahalanobis limit;
+// then the running sum of the regions' row tiles (kSlotRegions + 1 int32)
+// and the regions' row counts (kSlotRegions int32).
 constexpr int kStatF = 12 * 4 + 12 * 2 + 144 + 4;
-constexpr size_t kInferLds = (size_t)kWElems * 2 + (size_t)(kBias + kStatF) * sizeof(float);
+constexpr size_t kInferLds = (size_t)kWElems * 2 + (size_t)(kBias + kStatF) * sizeof(float) +
+                             (size_t)(2 * kSlotRegions + 1) * sizeof(int32_t);
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
@@ -196,6 +199,8 @@ __global__ __launch_bounds__(kInferWaves * 64) void surrogate_infer_kernel(const
     float *bias = reinterpret_cast<float *>(lds_raw + (size_t)kWElems * 2);
     float *x_mean = bias + kBias, *x_istd = x_mean + 12, *z_lo = x_istd + 12, *z_hi = z_lo + 12;
     float *y_mean = z_hi + 12, *y_std = y_mean + 12, *wht = y_std + 12, *maha = wht + 144;
+    int32_t *tile0 = reinterpret_cast<int32_t *>(bias + kBias + kStatF);
+    int32_t *rows_of = tile0 + kSlotRegions + 1;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int p = lane & 15, q = lane >> 4;
     const casim_mlp_stats *S = reinterpret_cast<const casim_mlp_stats *>(stats_raw);
@@ -220,6 +225,37 @@ __global__ __launch_bounds__(kInferWaves * 64) void surrogate_infer_kernel(const
         }
         for (int i = threadIdx.x; i < 144; i += blockDim.x) wht[i] = S->whiten[i];
         if (threadIdx.x == 0) maha[0] = maha_max_arg > 0.0f ? maha_max_arg : S->maha_q999;
+        // tile0[r]: the first of region r's tiles of kPts rows in one
+        // numbering of all regions' tiles (exclusive running sum over
+        // r < kSlotRegions; regions past nreg have none), tile0[kSlotRegions]
+        // their total.  The wavefronts of the grid take these tiles in turn,
+        // so every wavefront gets the same share whatever the regions' counts.
+        if (wv == 0) {
+            static_assert(kSlotRegions % 64 == 0, "regions are summed 64 lanes at a time");
+            constexpr int per = kSlotRegions / 64;
+            int32_t own[per], sum = 0;
+#pragma unroll
+            for (int j = 0; j < per; ++j) {
+                const int64_t r = (int64_t)lane * per + j;
+                const int32_t rows = r < nreg ? (int32_t)region_rows(counters, rcap, n_all, r) : 0;
+                rows_of[r] = rows;
+                own[j] = (rows + kPts - 1) / kPts;
+                sum += own[j];
+            }
+            int32_t incl = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t v = __shfl_up(incl, o);
+                if (lane >= o) incl += v;
+            }
+            int32_t run = incl - sum;
+#pragma unroll
+            for (int j = 0; j < per; ++j) {
+                tile0[lane * per + j] = run;
+                run += own[j];
+            }
+            if (lane == 63) tile0[kSlotRegions] = incl;
+        }
     }
     __syncthreads();
     const float maha_max = maha[0];
@@ -237,9 +273,22 @@ __global__ __launch_bounds__(kInferWaves * 64) void surrogate_infer_kernel(const
         wq[i] = p < 12 ? wht[p * 12 + f] : 0.0f;
     }
 
-    for (int64_t r = blockIdx.x; r < nreg; r += gridDim.x)
-    for (int64_t t = (int64_t)wv * kPts, cnt = region_rows(counters, rcap, n_all, r); t < cnt;
-         t += kInferWaves * kPts) {
+    const int64_t ntiles = tile0[kSlotRegions];
+    int lo = 0;                    // region of the wavefront's tile; tiles only move forward
+    for (int64_t g = (int64_t)blockIdx.x * kInferWaves + wv; g < ntiles; g += (int64_t)gridDim.x * kInferWaves) {
+        // the region of tile g is the last r with tile0[r] <= g (one with
+        // tiles, since tile0[r + 1] > g).  tile0 never decreases, so of the
+        // 64 entries after lo those at or below g are a prefix: the wave
+        // advances by their count, 64 at a time.
+        for (;;) {
+            const int idx = lo + 1 + lane;
+            const int adv = __popcll(__ballot(idx <= kSlotRegions && tile0[idx] <= g));
+            lo += adv;
+            if (adv < 64) break;
+        }
+        const int64_t r = lo;
+        const int64_t t = (g - tile0[lo]) * kPts;
+        const int64_t cnt = rows_of[lo];
         // ---- inputs: point 16 nt + p of the tile, features 4i + q ----------
         u32x4 b[4][kNT];
         int fb[kNT];
@@ -411,6 +460,7 @@ struct SurCtx {
     uint16_t *w = nullptr;
     float *bias = nullptr, *stats = nullptr;
     bool attr_set = false;
+    int cus = 0;                       // compute units of the device (grid of the inference kernel)
 };
 SurCtx SC;
 
@@ -453,7 +503,18 @@ hipError_t launch_surrogate_infer(const SurrogateDev &S, const float *feat, cons
         rcap = ((n + kSlotRegions - 1) / kSlotRegions + 63) / 64 * 64;
         nreg = (n + rcap - 1) / rcap;
     }
-    const int64_t blocks = nreg < 1 ? 1 : nreg;
+    // row counts per region and the tiles of all regions are numbered in int32
+    if (rcap > INT32_MAX || kSlotRegions * ((rcap + kPts - 1) / kPts) > INT32_MAX) return hipErrorInvalidValue;
+    // one block per compute unit (the LDS of one block), each block's
+    // wavefronts taking every (blocks x kInferWaves)-th tile
+    if (SC.cus <= 0) {
+        int dev = 0, cus = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        SC.cus = cus > 0 ? cus : 1;
+    }
+    const int64_t blocks = SC.cus;
     hipLaunchKernelGGL(surrogate_infer_kernel, dim3((unsigned)blocks), dim3(kInferWaves * 64), kInferLds, stream,
                        S.w, S.bias, S.stats, S.range_margin, S.maha_max, feat, gates, n, counters, rcap, nreg, rates,
                        fallback);
@@ -516,7 +577,7 @@ int casim_surrogate_load(void) {
 
 int casim_surrogate_infer(const float *feat, const uint16_t *gates, int64_t n, float *rates, uint8_t *fallback,
                           void *stream) {
-    if (!feat || !gates || !rates || !fallback || n < 0) return CASIM_EINVAL;
+    if (!feat || !gates || !rates || !fallback || n < 0 || n > ((int64_t)1 << 36)) return CASIM_EINVAL;
     if (((uintptr_t)feat | (uintptr_t)rates) & 15u) return CASIM_EINVAL;   // 16-byte row vectors
     if (!SC.ready) return CASIM_ENOSURROGATE;
     if (n == 0) return CASIM_OK;

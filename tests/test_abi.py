@@ -82,6 +82,7 @@ def test_surrogate_infer_rejects_misaligned_rows(L):
     ok, bad = vp(0x100000), vp(0x100004)
     assert L.casim_surrogate_infer(bad, ok, 64, ok, ok, None) == -1
     assert L.casim_surrogate_infer(ok, ok, 64, bad, ok, None) == -1
+    assert L.casim_surrogate_infer(ok, ok, (1 << 36) + 1, ok, ok, None) == -1
 
 
 def test_set_stats_rejects_a_whitening_factor_that_is_not_lower_triangular(L):
