@@ -69,6 +69,7 @@ __device__ __forceinline__ R clampv(R x, R lo, R hi) { return x < lo ? lo : (x >
 
 // The step reads each input and writes each tendency exactly once: streaming
 // (non-temporal) accesses keep them from displacing other lines in the caches.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ double ldnt(const double *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void stnt(double *p, double v) { __builtin_nontemporal_store(v, p); }
 
@@ -668,13 +669,24 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
                     plain = true;
                     // network rates for this point, unless it falls back
                     if (slot >= 0) {
-                        bool use = !a.sur_fallback[slot];
+                        // the slot's 12 rates (48 bytes: three 16-byte loads,
+                        // all of them whatever the gates, whose closed rates
+                        // are zero) and its flag, issued together and waited
+                        // for once (the empty asm keeps the compiler from
+                        // moving the rate loads behind the flag's test, which
+                        // costs a second round trip)
+                        const f32x4 *src = reinterpret_cast<const f32x4 *>(a.sur_rates + (int64_t)slot * 12);
+                        f32x4 v0 = src[0], v1 = src[1], v2 = src[2];
+                        int fbv = a.sur_fallback[slot];
+                        asm volatile("" : "+v"(v0), "+v"(v1), "+v"(v2), "+v"(fbv));
+                        bool use = fbv == 0;
                         if (use) {
                             const unsigned gb = gate_bits(P, warm, w, p, es_now);
+                            const float f[12] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3],
+                                                 v2[0], v2[1], v2[2], v2[3]};
                             double rr[12];
 #pragma unroll
-                            for (int j = 0; j < 12; ++j)
-                                rr[j] = ((gb >> j) & 1u) ? (double)a.sur_rates[(int64_t)slot * 12 + j] : 0.0;
+                            for (int j = 0; j < 12; ++j) rr[j] = ((gb >> j) & 1u) ? (double)f[j] : 0.0;
                             use = limiter_min_f(w, rr, dt) >= a.sur_f_min;
                             if (use) {
                                 apply_rates<double>(P, w, d, rr, dt);
