@@ -392,7 +392,7 @@ struct TileHistory {
 int plan_tiles_with(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, int32_t *busy, int32_t *order,
                     TileHistory &hist, hipStream_t st) {
     SweepGeometry geo;
-    HIP_TRY(sweep_geometry(ncol, a.nslots, a.mode, &geo));
+    HIP_TRY(sweep_geometry(ncol, a.nslots, nlev, a.mode, &geo));
     TilePlan tp;
     int rc = tile_plan(geo, tp);
     if (rc) return rc;
@@ -446,7 +446,7 @@ int scratch_setup(int dev) {
 
 int plan_tiles(const casim_state *s, int64_t ncol, int32_t nlev, SweepArgs &a, hipStream_t st) {
     SweepGeometry geo;
-    HIP_TRY(sweep_geometry(ncol, a.nslots, a.mode, &geo));
+    HIP_TRY(sweep_geometry(ncol, a.nslots, nlev, a.mode, &geo));
     int rc = ensure_tiles(geo.tiles);
     if (rc) return rc;
     if (!g.hist) g_hist.valid = false;
@@ -646,7 +646,7 @@ int casim_step_noalloc(const casim_state *s, int64_t ncol, int32_t nlev, double 
     a.nslots = slot;
     if (slot > kMaxCarrySlots) return CASIM_ECAPACITY;
     SweepGeometry geo;
-    HIP_TRY(sweep_geometry(ncol, a.nslots, a.mode, &geo));
+    HIP_TRY(sweep_geometry(ncol, a.nslots, nlev, a.mode, &geo));
     if (geo.tiles > kNoAllocMaxTiles) return CASIM_ECAPACITY;
     hipStream_t st = (hipStream_t)stream;
     // the vertical grid goes into the scratch with the step (4 KB at most)

@@ -202,9 +202,10 @@ constexpr int kCmpState = 13;
 // Launchers (casim_sweep.hip).  `fast` selects the kernels compiled with
 // kDefaultParams.  Return the launch's hipError_t.
 hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream);
-// Launch shape of the sweep for ncol columns and nslots carry slots
-// (hipErrorInvalidValue when the carries do not fit the LDS).
-hipError_t sweep_geometry(int64_t ncol, int32_t nslots, int mode, SweepGeometry *geo);
+// Launch shape of the sweep for ncol columns, nslots carry slots and nlev
+// levels (hipErrorInvalidValue when the carries and the layer thicknesses do
+// not fit the LDS).
+hipError_t sweep_geometry(int64_t ncol, int32_t nslots, int32_t nlev, int mode, SweepGeometry *geo);
 // Tile launch order from the previous step's per-tile activity, separately
 // for the wavefront positions each XCD runs (see virtual_block): busy tiles
 // and most clear ones in index order, the XCD's last `reserve` clear tiles

@@ -506,8 +506,13 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
     constexpr int L = kWave / C;
     constexpr bool FAST = VAR != VAR_GENERIC;
     const DevParams &P = params<FAST>(Prt);
-    load_math_tables();
     extern __shared__ double lds_all[];
+    // the layer thicknesses, one copy per block after its wavefronts' carries
+    // (read per busy chunk; a global load there would wait on the vector
+    // memory counter, and with it on the next chunk's loads)
+    double *lds_dz = lds_all + (size_t)(blockDim.x / kWave) * (a.nslots + 8) * C;
+    for (int j = threadIdx.x; j < a.nlev; j += blockDim.x) lds_dz[j] = a.dz[j];
+    load_math_tables();          // ends with a block barrier
     const int lane = threadIdx.x & (kWave - 1);
     const int wib = threadIdx.x / kWave;
     const int g = lane / C, c = lane % C;
@@ -708,7 +713,7 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
         bool out_nz = false;
         if (do_sed) {
             double inv_rdz = 0.0;
-            if (need) inv_rdz = rcp64(rho * a.dz[k < 0 ? 0 : k]);
+            if (need) inv_rdz = rcp64(rho * lds_dz[k < 0 ? 0 : k]);
             const bool surf = vp && k == 0;
             unsigned cc = 0;
             cc |= sediment<R, C>(P, 0, a.nsub[0], a.dts[0], lds + a.slot0[0] * C, g, c, need, rho, ln_rho,
@@ -1085,17 +1090,18 @@ int columns_per_wave(int64_t ncol, int mode) {
 
 }  // namespace
 
-hipError_t sweep_geometry(int64_t ncol, int32_t nslots, int mode, SweepGeometry *geo) {
+hipError_t sweep_geometry(int64_t ncol, int32_t nslots, int32_t nlev, int mode, SweepGeometry *geo) {
     const int C = columns_per_wave(ncol, mode);
     // narrow tiles: enough wavefronts per block to cover whole 128-byte rows,
     // so the halves of a line are fetched by one CU
     int wpb = env_int("CASIM_WAVES_PER_BLOCK", C >= 16 ? 1 : 16 / C);
     if (wpb < 1 || wpb > 4) wpb = 1;
     const size_t per_wave = (size_t)(nslots + 8) * C * sizeof(double);   // carries + surface sums
-    size_t lds = (size_t)wpb * per_wave;
+    const size_t dz_bytes = (size_t)nlev * sizeof(double);                 // layer thicknesses
+    size_t lds = (size_t)wpb * per_wave + dz_bytes;
     // 64 KiB per block, the math tables included
     const size_t lds_max = 65536 - kMathLdsBytes;
-    while (wpb > 1 && lds > lds_max) { --wpb; lds = (size_t)wpb * per_wave; }
+    while (wpb > 1 && lds > lds_max) { --wpb; lds = (size_t)wpb * per_wave + dz_bytes; }
     if (lds > lds_max) return hipErrorInvalidValue;
     geo->C = C;
     geo->wpb = wpb;
@@ -1107,7 +1113,7 @@ hipError_t sweep_geometry(int64_t ncol, int32_t nslots, int mode, SweepGeometry 
 
 hipError_t launch_sweep(const DevParams &P, bool fast, const SweepArgs &a, hipStream_t stream) {
     SweepGeometry geo;
-    const hipError_t ge = sweep_geometry(a.ncol, a.nslots, a.mode, &geo);
+    const hipError_t ge = sweep_geometry(a.ncol, a.nslots, a.nlev, a.mode, &geo);
     if (ge != hipSuccess) return ge;
     if ((a.order || a.tile_busy) && a.ntiles != geo.tiles) return hipErrorInvalidValue;
     if (a.nxcd < 1 || a.xcd_group < 1) return hipErrorInvalidValue;
