@@ -507,16 +507,17 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
     constexpr bool FAST = VAR != VAR_GENERIC;
     const DevParams &P = params<FAST>(Prt);
     extern __shared__ double lds_all[];
-    // the layer thicknesses, one copy per block after its wavefronts' carries
-    // (read per busy chunk; a global load there would wait on the vector
-    // memory counter, and with it on the next chunk's loads)
-    double *lds_dz = lds_all + (size_t)(blockDim.x / kWave) * (a.nslots + 8) * C;
+    // the layer thicknesses, one copy per block at the start of the dynamic
+    // LDS (a fixed address: no register holds it), the wavefronts' carries
+    // after them (read per busy chunk; a global load there would wait on the
+    // vector memory counter, and with it on the next chunk's loads)
+    double *const lds_dz = lds_all;
     for (int j = threadIdx.x; j < a.nlev; j += blockDim.x) lds_dz[j] = a.dz[j];
     load_math_tables();          // ends with a block barrier
     const int lane = threadIdx.x & (kWave - 1);
     const int wib = threadIdx.x / kWave;
     const int g = lane / C, c = lane % C;
-    double *lds = lds_all + (size_t)wib * (a.nslots + 8) * C;
+    double *lds = lds_all + a.nlev + (size_t)wib * (a.nslots + 8) * C;
     // wavefront -> tile of C columns: the virtual position of the wavefront
     // (XCD groups, see virtual_block), then the launch order derived from the
     // previous step's activity, else the identity (a corrupt entry falls back
