@@ -577,6 +577,17 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
         }
         return v;
     };
+    // the 6 other fields of the next chunk into v (for a lane whose column is busy)
+    auto load_extra = [&](Ahead &v, int kk0) {
+        const int kk = kk0 - g;
+        if (colvalid && kk >= 0) {
+            const int64_t jx = (int64_t)kk * a.ld + col;
+            v.rho = ldnt(a.in[2] + jx);
+            v.nc = ldnt(a.in[5] + jx); v.nr = ldnt(a.in[7] + jx);
+            if (!warm) { v.ni = ldnt(a.in[9] + jx); v.ns = ldnt(a.in[11] + jx); v.ng = ldnt(a.in[13] + jx); }
+            v.extra = true;
+        }
+    };
     Ahead nxt = load_ahead(a.nlev - 1, false);
 
     for (int k0 = a.nlev - 1; k0 >= 0; k0 -= L) {
@@ -650,7 +661,7 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
         // physics (longest cover of their latency); the mixed kernel issues them
         // after it, which keeps them out of the registers of the rate block and
         // lets the kernel fit 128 VGPRs (4 wavefronts per SIMD; measured faster).
-        if constexpr (!MIX) nxt = load_ahead(k0 - L, col_busy);
+        if constexpr (!MIX) nxt = load_ahead(k0 - L, false);
         if (need) ln_rho = log64(rho);
         const double rfac = ::sqrt(P.rho_0 * rcp64(rho));
         const int slot = cur.slot;
@@ -711,6 +722,7 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
             }
         }
         if constexpr (MIX) nxt = load_ahead(k0 - L, col_busy);
+        else if (col_busy) load_extra(nxt, k0 - L);
         bool out_nz = false;
         if (do_sed) {
             double inv_rdz = 0.0;
