@@ -657,10 +657,12 @@ __global__ __launch_bounds__(256, (MIX && VAR != VAR_GENERIC) ? 4 : 3) void swee
                 if (!warm) { w.ni = a.in[9][ix]; w.ns = a.in[11][ix]; w.ng = a.in[13][ix]; }
             }
         }
-        // The binary64 kernel issues the next chunk's loads before the point
-        // physics (longest cover of their latency); the mixed kernel issues them
-        // after it, which keeps them out of the registers of the rate block and
-        // lets the kernel fit 128 VGPRs (4 wavefronts per SIMD; measured faster).
+        // The binary64 kernel issues the next chunk's 8 activity fields before
+        // the point physics (longest cover of their latency) and its other 6
+        // after it: all 14 held through the physics spilled registers.  The
+        // mixed kernel issues all of them after it, which keeps them out of
+        // the registers of the rate block and lets the kernel fit 128 VGPRs
+        // (4 wavefronts per SIMD; measured faster).
         if constexpr (!MIX) nxt = load_ahead(k0 - L, false);
         if (need) ln_rho = log64(rho);
         const double rfac = ::sqrt(P.rho_0 * rcp64(rho));
