@@ -460,7 +460,7 @@ struct SurCtx {
     uint16_t *w = nullptr;
     float *bias = nullptr, *stats = nullptr;
     bool attr_set = false;
-    int cus = 0;                       // compute units of the device (grid of the inference kernel)
+    int cus = 0, cus_device = -1;      // compute units of device cus_device (grid of the inference kernel)
 };
 SurCtx SC;
 
@@ -507,12 +507,15 @@ hipError_t launch_surrogate_infer(const SurrogateDev &S, const float *feat, cons
     if (rcap > INT32_MAX || kSlotRegions * ((rcap + kPts - 1) / kPts) > INT32_MAX) return hipErrorInvalidValue;
     // one block per compute unit (the LDS of one block), each block's
     // wavefronts taking every (blocks x kInferWaves)-th tile
-    if (SC.cus <= 0) {
-        int dev = 0, cus = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
+    int dev = 0;
+    hipError_t de = hipGetDevice(&dev);
+    if (de != hipSuccess) return de;
+    if (SC.cus <= 0 || SC.cus_device != dev) {
+        int cus = 0;
+        de = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (de != hipSuccess) return de;
         SC.cus = cus > 0 ? cus : 1;
+        SC.cus_device = dev;
     }
     const int64_t blocks = SC.cus;
     hipLaunchKernelGGL(surrogate_infer_kernel, dim3((unsigned)blocks), dim3(kInferWaves * 64), kInferLds, stream,
