@@ -142,7 +142,7 @@ typedef struct casim_thresholds {
  *   dz      : HOST pointer to nlev layer thicknesses (m), read during the
  *             call; the library keeps a device copy.
  *   ld      : leading dimension (>= ncol) of every 3-D field; columns
- *             ld - ncol .. of a row are never read or written.  Prefer the
+ *             ncol .. ld-1 of a row are never read or written.  Prefer the
  *             value casim_padded_ld recommends (a row stride that is a
  *             multiple of 4 KB is measurably slower).
  *   tend[12]: dT, dqv, dqc, dnc, dqr, dnr, dqi, dni, dqs, dns, dqg, dng, per
