@@ -275,6 +275,14 @@ def _rows_ok(t, ld):
     return ld >= width and (nf <= 1 or t.stride(0) >= (rows - 1) * ld + width)
 
 
+def _check_ncol(ncol, state):
+    """The step covers columns 0 .. ncol-1 of the fields: no more than the
+    tensor holds (the library would otherwise touch the columns past a view,
+    which need not belong to its storage)."""
+    if not 0 <= ncol <= state.shape[2]:
+        raise ValueError("ncol = %d is outside the fields' %d columns" % (ncol, state.shape[2]))
+
+
 def _check_tensors(state, tend, sfc, ncol):
     """Validate device fields; returns (nlev, ld, ncol) as _layout does."""
     import torch
@@ -284,6 +292,7 @@ def _check_tensors(state, tend, sfc, ncol):
         if t.shape[0] != lead:
             raise ValueError("%s must have %d fields" % (name, lead))
     nlev, ld, ncol = _layout(state, ncol)
+    _check_ncol(ncol, state)
     if state.shape[1:] != tend.shape[1:]:
         raise ValueError("state and tend must share (nlev, columns)")
     if not (_rows_ok(state, ld) and _rows_ok(tend, ld)):
@@ -460,6 +469,7 @@ def surrogate_rates(state, dz, dt, rates, flags, ncol=None, stream=None):
             and state.dim() == 3 and state.shape[0] == NIN):
         raise ValueError("state must be a (14, nlev, columns) float64 cuda tensor")
     nlev, ld, ncol = _layout(state, ncol)
+    _check_ncol(ncol, state)
     if not _rows_ok(state, ld):
         raise ValueError("state needs unit column stride and one level stride (the leading dimension)")
     if not (rates.is_cuda and rates.dtype == torch.float32 and rates.is_contiguous()

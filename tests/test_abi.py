@@ -150,3 +150,15 @@ def test_binding_refuses_host_arrays_as_device_fields():
     for fn in (casim.step, casim.step_noalloc, casim.apply_tendencies, casim.debug_stream):
         with pytest.raises(ValueError):
             fn(x, [1.0, 1.0, 1.0], 1.0, t, s)
+
+
+def test_binding_refuses_more_columns_than_the_fields_hold():
+    """ncol may cover a prefix of the fields' columns, never more: columns past
+    a view need not belong to its storage."""
+    import torch
+    x = torch.zeros((14, 3, 8), dtype=torch.float64)
+    for n in (0, 5, 8):
+        casim._check_ncol(n, x)
+    for n in (-1, 9):
+        with pytest.raises(ValueError):
+            casim._check_ncol(n, x)

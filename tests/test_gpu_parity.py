@@ -326,3 +326,5 @@ def test_padded_view_layout_matches_contiguous():
         casim.step(sbuf[:, :, 0:ncol:2], dz, cfg.dt, tbuf[:, :, 0:ncol:2], sfc)
     with pytest.raises(ValueError):       # tendencies with another leading dimension
         casim.step(dev, dz, cfg.dt, tend.contiguous(), sfc)
+    with pytest.raises(ValueError):       # more columns than the view holds
+        casim.step(dev, dz, cfg.dt, tend, sfc.new_zeros((8, ncol + 1)), ncol=ncol + 1)
