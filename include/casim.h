@@ -200,7 +200,10 @@ int casim_step(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void
  * All calls on one GPU share that array and it keeps the last call's
  * contents: calls whose execution overlaps on one GPU (other streams, other
  * host threads) race on it and must be ordered by the caller.  dz is a host
- * pointer, copied to the array with an asynchronous copy on `stream`.
+ * pointer, copied to the array with an asynchronous copy on `stream`: keep
+ * it valid and unchanged until that copy has run (page-locked memory is read
+ * when the stream reaches the copy; under graph capture the recorded copy
+ * reads it again at every replay).
  * Errors: as casim_step. */
 int casim_step_noalloc(const casim_state *s, int64_t ncol, int32_t nlev, double dt, void *stream);
 
